@@ -1,0 +1,653 @@
+/*
+ * vtx_oracle.c -- plain FP64 CPU reference of the periodic 2-D vertex model.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * checked against; it shares no code, header, table or helper with the
+ * library under paper_2604_06896_amd/csrc, and nothing in the product path
+ * may call it.  Only tests/, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.
+ *
+ * Everything here is written for a reader checking it against the paper by
+ * eye: plain loops, FP64 throughout, no blocking, no fusion, no reordering
+ * beyond what the definitions state.
+ *
+ * Sources (VertAX, arXiv 2604.06896):
+ *   - half-edge table with 8 columns (prev, next, twin, source, target,
+ *     face, x-offset, y-offset of the target): Methods, "System state and
+ *     data structure";
+ *   - periodic boundary, target offsets in {-1,0,1}: Methods, "Periodic mode";
+ *   - energy  E = sum_cells K_A (A-A0)^2 + K_P (P-P0)^2 + sum_edges lambda*l:
+ *     Methods, "Vertex model formulation", equations E1 and E2 (the line
+ *     tension term of E2 added to E1);
+ *   - gradient-descent relaxation X <- X - eta grad E, stopped when the max
+ *     nodal force stays below a tolerance over a patience window or at a
+ *     maximum iteration count: Methods, "Simulation engine";
+ *   - T1 transitions (edges checked one after the other, short edge either
+ *     stretched along its orientation or replaced by an orthogonal edge,
+ *     lower total energy wins): Methods, "T1 transitions";
+ *   - implicit differentiation  grad_theta C = d_theta C
+ *       - (d2E/dX dtheta)^T H^-1 grad_X C: Methods, "Implicit
+ *     differentiation (ID)";
+ *   - equilibrium propagation, centred estimator with nudges +-beta/2:
+ *     Methods, "Equilibrium propagation (EP)";
+ *   - v2v cost C = 1/(2N) sum |x - x_target|^2: Methods, "Geometric
+ *     vertex-to-vertex (v2v) cost".
+ *
+ * Readings of points the paper leaves open:
+ *   - edges are numbered by ascending lower half-edge id of the twin pair;
+ *   - the convergence test uses the max over all 2N force components;
+ *   - the T1 pass visits edges in ascending edge id and uses the current
+ *     positions and topology for each edge; the trigger is strict
+ *     (l < l_min); both candidates place the two vertices l_new apart around
+ *     the old midpoint; the T1 candidate is taken only if its total energy
+ *     is strictly lower; it is not considered when one of the two cells
+ *     losing the edge has 3 sides or when the four cells around the edge are
+ *     not distinct; the new edge keeps the edge id and lambda of the old one;
+ *   - relaxation order per iteration: T1 pass, forces, convergence test,
+ *     step;
+ *   - the Hessian of a periodic tissue has the two rigid translations as
+ *     null vectors; the adjoint system is solved on the zero-mean subspace
+ *     (right-hand side projected, solution projected);
+ *   - the v2v displacement uses the minimum periodic image;
+ *   - the EP nudge force has its mean removed (see add_nudge).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { PREV = 0, NEXT, TWIN, SRC, TGT, FACE, OX, OY };
+
+typedef struct {
+    int32_t *he;      /* [n_he][8] */
+    int64_t n_he, n_vert, n_cell;
+    double Lx, Ly;
+} ora_mesh;
+
+typedef struct {
+    const double *KA, *A0, *KP, *P0; /* [n_cell] */
+    const double *lam;               /* [n_edge] */
+} ora_par;
+
+typedef struct {
+    double eta, tol;
+    int64_t patience, max_iter;
+    int32_t t1_enable;
+    double l_min, l_new;
+    double beta;             /* nudge strength (0 = none)               */
+    const double *X_target;  /* v2v nudge target [n_vert][2], or NULL   */
+    const double *g_lin;     /* linear nudge vector [n_vert][2], or NULL */
+} ora_relax_opts;
+
+typedef struct {
+    int64_t iters, n_t1, n_stretch;
+    double max_f, energy;
+    int32_t status;          /* 0 converged, 1 not converged */
+} ora_relax_out;
+
+#define HE(m, h, c) ((m)->he[(int64_t)(h) * 8 + (c)])
+
+/* ---------------------------------------------------------------- edges */
+
+/* Edge e is the e-th twin pair in ascending order of its lower half-edge. */
+int64_t ora_edge_index(const ora_mesh *m, int64_t *edge_of_he, int64_t *he_of_edge)
+{
+    int64_t e = 0;
+    for (int64_t h = 0; h < m->n_he; ++h) {
+        int64_t t = HE(m, h, TWIN);
+        if (h < t) {
+            if (edge_of_he) { edge_of_he[h] = e; edge_of_he[t] = e; }
+            if (he_of_edge) he_of_edge[e] = h;
+            ++e;
+        }
+    }
+    return e;
+}
+
+/* Edge vector of half-edge h: target (shifted by its image offset) minus
+ * source. */
+static void edge_vec(const ora_mesh *m, const double *X, int64_t h, double d[2])
+{
+    int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+    d[0] = X[2 * t] + HE(m, h, OX) * m->Lx - X[2 * s];
+    d[1] = X[2 * t + 1] + HE(m, h, OY) * m->Ly - X[2 * s + 1];
+}
+
+void ora_edge_lengths(const ora_mesh *m, const double *X, double *len)
+{
+    int64_t n_e = m->n_he / 2;
+    int64_t *hoe = malloc(sizeof(int64_t) * (n_e + 1));
+    n_e = ora_edge_index(m, NULL, hoe);
+    for (int64_t e = 0; e < n_e; ++e) {
+        double d[2];
+        edge_vec(m, X, hoe[e], d);
+        len[e] = sqrt(d[0] * d[0] + d[1] * d[1]);
+    }
+    free(hoe);
+}
+
+/* First (lowest-id) half-edge of every cell. */
+static void first_half_edges(const ora_mesh *m, int64_t *first)
+{
+    for (int64_t c = 0; c < m->n_cell; ++c) first[c] = -1;
+    for (int64_t h = 0; h < m->n_he; ++h) {
+        int64_t c = HE(m, h, FACE);
+        if (first[c] < 0) first[c] = h;
+    }
+}
+
+/* ------------------------------------------------------- cell geometry */
+
+/* Area (shoelace on the unwrapped polygon, translation invariant) and
+ * perimeter of every cell.  r_0 = 0, r_{k+1} = r_k + d_k,
+ * A = 1/2 sum_k r_k x r_{k+1},  P = sum_k |d_k|. */
+void ora_cells(const ora_mesh *m, const double *X, double *A, double *P, int32_t *nsides)
+{
+    int64_t *first = malloc(sizeof(int64_t) * m->n_cell);
+    first_half_edges(m, first);
+    for (int64_t c = 0; c < m->n_cell; ++c) {
+        double rx = 0.0, ry = 0.0, a = 0.0, p = 0.0;
+        int32_t n = 0;
+        int64_t h = first[c];
+        do {
+            double d[2];
+            edge_vec(m, X, h, d);
+            double nx = rx + d[0], ny = ry + d[1];
+            a += 0.5 * (rx * ny - ry * nx);
+            p += sqrt(d[0] * d[0] + d[1] * d[1]);
+            rx = nx; ry = ny;
+            ++n;
+            h = HE(m, h, NEXT);
+        } while (h != first[c]);
+        if (A) A[c] = a;
+        if (P) P[c] = p;
+        if (nsides) nsides[c] = n;
+    }
+    free(first);
+}
+
+/* ---------------------------------------------------------------- energy */
+
+double ora_energy(const ora_mesh *m, const double *X, const ora_par *p)
+{
+    double *A = malloc(sizeof(double) * m->n_cell);
+    double *P = malloc(sizeof(double) * m->n_cell);
+    ora_cells(m, X, A, P, NULL);
+    double E = 0.0;
+    for (int64_t c = 0; c < m->n_cell; ++c) {
+        double da = A[c] - p->A0[c], dp = P[c] - p->P0[c];
+        E += p->KA[c] * da * da + p->KP[c] * dp * dp;
+    }
+    int64_t n_e = m->n_he / 2;
+    double *len = malloc(sizeof(double) * n_e);
+    ora_edge_lengths(m, X, len);
+    for (int64_t e = 0; e < n_e; ++e) E += p->lam[e] * len[e];
+    free(A); free(P); free(len);
+    return E;
+}
+
+/* Energy and forces F = -grad_X E.
+ *   grad_k A = 1/2 R(x_{k+1} - x_{k-1}),  R(a) = (a_y, -a_x)
+ *   grad P   = sum over the cell's edges of grad l
+ *   grad l (edge s->t, d = x_t - x_s): -d/l at s, +d/l at t
+ * Each cell adds 2K_A(A-A0) grad A + 2K_P(P-P0) grad P; each edge adds
+ * lambda grad l. */
+double ora_energy_forces(const ora_mesh *m, const double *X, const ora_par *p, double *F)
+{
+    int64_t nv = m->n_vert;
+    double *g = calloc(2 * nv, sizeof(double));
+    double *A = malloc(sizeof(double) * m->n_cell);
+    double *P = malloc(sizeof(double) * m->n_cell);
+    int64_t *first = malloc(sizeof(int64_t) * m->n_cell);
+    ora_cells(m, X, A, P, NULL);
+    first_half_edges(m, first);
+    double E = 0.0;
+    for (int64_t c = 0; c < m->n_cell; ++c) {
+        double da = A[c] - p->A0[c], dp = P[c] - p->P0[c];
+        E += p->KA[c] * da * da + p->KP[c] * dp * dp;
+        double cA = 2.0 * p->KA[c] * da, cP = 2.0 * p->KP[c] * dp;
+        int64_t h = first[c];
+        do {
+            double d[2], dprev[2];
+            edge_vec(m, X, h, d);
+            edge_vec(m, X, HE(m, h, PREV), dprev);
+            int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+            /* corner s: x_next - x_prev = d + dprev */
+            double ax = d[0] + dprev[0], ay = d[1] + dprev[1];
+            g[2 * s] += cA * 0.5 * ay;
+            g[2 * s + 1] += cA * 0.5 * (-ax);
+            /* perimeter through this edge */
+            double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+            g[2 * s] -= cP * d[0] / l;
+            g[2 * s + 1] -= cP * d[1] / l;
+            g[2 * t] += cP * d[0] / l;
+            g[2 * t + 1] += cP * d[1] / l;
+            h = HE(m, h, NEXT);
+        } while (h != first[c]);
+    }
+    int64_t n_e = m->n_he / 2;
+    int64_t *hoe = malloc(sizeof(int64_t) * (n_e + 1));
+    n_e = ora_edge_index(m, NULL, hoe);
+    for (int64_t e = 0; e < n_e; ++e) {
+        int64_t h = hoe[e];
+        double d[2];
+        edge_vec(m, X, h, d);
+        double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+        int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+        E += p->lam[e] * l;
+        g[2 * s] -= p->lam[e] * d[0] / l;
+        g[2 * s + 1] -= p->lam[e] * d[1] / l;
+        g[2 * t] += p->lam[e] * d[0] / l;
+        g[2 * t + 1] += p->lam[e] * d[1] / l;
+    }
+    if (F)
+        for (int64_t k = 0; k < 2 * nv; ++k) F[k] = -g[k];
+    free(g); free(A); free(P); free(first); free(hoe);
+    return E;
+}
+
+/* ------------------------------------------------------------------- HVP */
+
+/* Hessian-vector product H v = d/de grad E(X + e v) at e = 0, term by term:
+ *   cell:  2K_A dA[v] grad A + c_A d(grad A)[v]
+ *        + 2K_P dP[v] grad P + c_P d(grad P)[v]
+ *   edge:  lambda d(grad l)[v]
+ * with dA[v] = sum_k grad_k A . v_k, d(grad_k A)[v] = 1/2 R(v_{k+1}-v_{k-1}),
+ * dl[v] = u.(v_t - v_s) and d(u)[v] = (I - u u^T)(v_t - v_s)/l, u = d/l. */
+void ora_hvp(const ora_mesh *m, const double *X, const ora_par *p, const double *v, double *Hv)
+{
+    int64_t nv = m->n_vert;
+    for (int64_t k = 0; k < 2 * nv; ++k) Hv[k] = 0.0;
+    double *A = malloc(sizeof(double) * m->n_cell);
+    double *P = malloc(sizeof(double) * m->n_cell);
+    int64_t *first = malloc(sizeof(int64_t) * m->n_cell);
+    ora_cells(m, X, A, P, NULL);
+    first_half_edges(m, first);
+    for (int64_t c = 0; c < m->n_cell; ++c) {
+        double cA = 2.0 * p->KA[c] * (A[c] - p->A0[c]);
+        double cP = 2.0 * p->KP[c] * (P[c] - p->P0[c]);
+        /* first pass: directional derivatives dA[v], dP[v] */
+        double dA = 0.0, dP = 0.0;
+        int64_t h = first[c];
+        do {
+            double d[2], dprev[2];
+            edge_vec(m, X, h, d);
+            edge_vec(m, X, HE(m, h, PREV), dprev);
+            int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+            double ax = d[0] + dprev[0], ay = d[1] + dprev[1];
+            dA += 0.5 * ay * v[2 * s] + 0.5 * (-ax) * v[2 * s + 1];
+            double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+            dP += (d[0] * (v[2 * t] - v[2 * s]) + d[1] * (v[2 * t + 1] - v[2 * s + 1])) / l;
+            h = HE(m, h, NEXT);
+        } while (h != first[c]);
+        /* second pass: assemble */
+        h = first[c];
+        do {
+            double d[2], dprev[2];
+            edge_vec(m, X, h, d);
+            edge_vec(m, X, HE(m, h, PREV), dprev);
+            int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+            int64_t sp = HE(m, HE(m, h, PREV), SRC); /* previous corner */
+            /* area: grad_s A and its derivative */
+            double ax = d[0] + dprev[0], ay = d[1] + dprev[1];
+            double gAx = 0.5 * ay, gAy = -0.5 * ax;
+            double wx = v[2 * t] - v[2 * sp], wy = v[2 * t + 1] - v[2 * sp + 1];
+            Hv[2 * s] += 2.0 * p->KA[c] * dA * gAx + cA * 0.5 * wy;
+            Hv[2 * s + 1] += 2.0 * p->KA[c] * dA * gAy + cA * 0.5 * (-wx);
+            /* perimeter through this edge: grad l = -u at s, +u at t */
+            double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+            double ux = d[0] / l, uy = d[1] / l;
+            double rx = v[2 * t] - v[2 * s], ry = v[2 * t + 1] - v[2 * s + 1];
+            double ru = rx * ux + ry * uy;
+            double dux = (rx - ru * ux) / l, duy = (ry - ru * uy) / l;
+            Hv[2 * s] += 2.0 * p->KP[c] * dP * (-ux) + cP * (-dux);
+            Hv[2 * s + 1] += 2.0 * p->KP[c] * dP * (-uy) + cP * (-duy);
+            Hv[2 * t] += 2.0 * p->KP[c] * dP * ux + cP * dux;
+            Hv[2 * t + 1] += 2.0 * p->KP[c] * dP * uy + cP * duy;
+            h = HE(m, h, NEXT);
+        } while (h != first[c]);
+    }
+    int64_t n_e = m->n_he / 2;
+    int64_t *hoe = malloc(sizeof(int64_t) * (n_e + 1));
+    n_e = ora_edge_index(m, NULL, hoe);
+    for (int64_t e = 0; e < n_e; ++e) {
+        int64_t h = hoe[e];
+        double d[2];
+        edge_vec(m, X, h, d);
+        int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+        double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+        double ux = d[0] / l, uy = d[1] / l;
+        double rx = v[2 * t] - v[2 * s], ry = v[2 * t + 1] - v[2 * s + 1];
+        double ru = rx * ux + ry * uy;
+        double dux = (rx - ru * ux) / l, duy = (ry - ru * uy) / l;
+        Hv[2 * s] -= p->lam[e] * dux;
+        Hv[2 * s + 1] -= p->lam[e] * duy;
+        Hv[2 * t] += p->lam[e] * dux;
+        Hv[2 * t + 1] += p->lam[e] * duy;
+    }
+    free(A); free(P); free(first); free(hoe);
+}
+
+/* ------------------------------------------------- mixed second derivatives */
+
+/* (d2E / dX dlambda_e) . mu = grad_X l_e . mu = u_e . (mu_t - mu_s). */
+void ora_mixed_lambda(const ora_mesh *m, const double *X, const double *mu, double *out)
+{
+    int64_t n_e = m->n_he / 2;
+    int64_t *hoe = malloc(sizeof(int64_t) * (n_e + 1));
+    n_e = ora_edge_index(m, NULL, hoe);
+    for (int64_t e = 0; e < n_e; ++e) {
+        int64_t h = hoe[e];
+        double d[2];
+        edge_vec(m, X, h, d);
+        int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+        double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+        out[e] = (d[0] * (mu[2 * t] - mu[2 * s]) + d[1] * (mu[2 * t + 1] - mu[2 * s + 1])) / l;
+    }
+    free(hoe);
+}
+
+/* (d2E / dX dP0_c) . mu = -2 K_P grad_X P_c . mu. */
+void ora_mixed_p0(const ora_mesh *m, const double *X, const ora_par *p, const double *mu, double *out)
+{
+    int64_t *first = malloc(sizeof(int64_t) * m->n_cell);
+    first_half_edges(m, first);
+    for (int64_t c = 0; c < m->n_cell; ++c) {
+        double dP = 0.0;
+        int64_t h = first[c];
+        do {
+            double d[2];
+            edge_vec(m, X, h, d);
+            int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
+            double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+            dP += (d[0] * (mu[2 * t] - mu[2 * s]) + d[1] * (mu[2 * t + 1] - mu[2 * s + 1])) / l;
+            h = HE(m, h, NEXT);
+        } while (h != first[c]);
+        out[c] = -2.0 * p->KP[c] * dP;
+    }
+    free(first);
+}
+
+/* ------------------------------------------------------------- v2v cost */
+
+static double min_image(double d, double L) { return d - L * floor(d / L + 0.5); }
+
+/* C = 1/(2N) sum_k |x_k - t_k|^2 (minimum image);  grad_k C = (x_k - t_k)/N. */
+double ora_v2v(const ora_mesh *m, const double *X, const double *Xt, double *grad)
+{
+    int64_t nv = m->n_vert;
+    double C = 0.0;
+    for (int64_t k = 0; k < nv; ++k) {
+        double dx = min_image(X[2 * k] - Xt[2 * k], m->Lx);
+        double dy = min_image(X[2 * k + 1] - Xt[2 * k + 1], m->Ly);
+        C += dx * dx + dy * dy;
+        if (grad) { grad[2 * k] = dx / (double)nv; grad[2 * k + 1] = dy / (double)nv; }
+    }
+    return C / (2.0 * (double)nv);
+}
+
+/* ------------------------------------------------------------------- T1 */
+
+static int64_t face_sides(const ora_mesh *m, int64_t h0)
+{
+    int64_t n = 0, h = h0;
+    do { ++n; h = HE(m, h, NEXT); } while (h != h0 && n <= m->n_he);
+    return n;
+}
+
+/* Whether the neighbour exchange of the edge of half-edge h is admissible:
+ * the four cells around the edge are distinct and neither cell that loses
+ * the edge is a triangle. */
+int ora_t1_admissible(const ora_mesh *m, int64_t h)
+{
+    int64_t t = HE(m, h, TWIN);
+    int64_t C1 = HE(m, h, FACE), C2 = HE(m, t, FACE);
+    int64_t C3 = HE(m, HE(m, HE(m, h, PREV), TWIN), FACE);
+    int64_t C4 = HE(m, HE(m, HE(m, h, NEXT), TWIN), FACE);
+    if (C1 == C2 || C1 == C3 || C1 == C4 || C2 == C3 || C2 == C4 || C3 == C4) return 0;
+    if (face_sides(m, h) <= 3 || face_sides(m, t) <= 3) return 0;
+    return 1;
+}
+
+/* Topology of the neighbour exchange of edge (h: i->j in C1, t: j->i in C2).
+ * C3 is the third cell at i, C4 the third cell at j.  Afterwards C1 and C2
+ * no longer share an edge; h (i->j) bounds C4 and t (j->i) bounds C3; i is
+ * the corner of C1, C3, C4 and j the corner of C2, C3, C4.  With
+ *   p1 = prev(h) (a->i), n1 = next(h) (j->c)   in C1,
+ *   p2 = prev(t) (d->j), n2 = next(t) (i->b)   in C2,
+ * the edge to c moves from j to i and the edge to b from i to j; image
+ * offsets of the moved half-edges change by the offset of h so that every
+ * edge vector is unchanged. */
+void ora_t1_topology(ora_mesh *m, int64_t h)
+{
+    int64_t t = HE(m, h, TWIN);
+    int64_t i = HE(m, h, SRC), j = HE(m, h, TGT);
+    int64_t C3 = HE(m, HE(m, HE(m, h, PREV), TWIN), FACE);
+    int64_t C4 = HE(m, HE(m, HE(m, h, NEXT), TWIN), FACE);
+    int64_t p1 = HE(m, h, PREV), n1 = HE(m, h, NEXT);
+    int64_t p2 = HE(m, t, PREV), n2 = HE(m, t, NEXT);
+    int64_t tp1 = HE(m, p1, TWIN), tn1 = HE(m, n1, TWIN);
+    int64_t tp2 = HE(m, p2, TWIN), tn2 = HE(m, n2, TWIN);
+    int32_t hox = HE(m, h, OX), hoy = HE(m, h, OY);
+    /* C1: a->i -> i->c */
+    HE(m, p1, NEXT) = (int32_t)n1; HE(m, n1, PREV) = (int32_t)p1;
+    HE(m, n1, SRC) = (int32_t)i;   HE(m, tn1, TGT) = (int32_t)i;
+    HE(m, n1, OX) += hox; HE(m, n1, OY) += hoy;
+    HE(m, tn1, OX) = -HE(m, n1, OX); HE(m, tn1, OY) = -HE(m, n1, OY);
+    /* C2: d->j -> j->b */
+    HE(m, p2, NEXT) = (int32_t)n2; HE(m, n2, PREV) = (int32_t)p2;
+    HE(m, n2, SRC) = (int32_t)j;   HE(m, tn2, TGT) = (int32_t)j;
+    HE(m, n2, OX) -= hox; HE(m, n2, OY) -= hoy;
+    HE(m, tn2, OX) = -HE(m, n2, OX); HE(m, tn2, OY) = -HE(m, n2, OY);
+    /* C4: c->i -> i->j -> j->d */
+    HE(m, tn1, NEXT) = (int32_t)h; HE(m, h, PREV) = (int32_t)tn1;
+    HE(m, h, NEXT) = (int32_t)tp2; HE(m, tp2, PREV) = (int32_t)h;
+    HE(m, h, FACE) = (int32_t)C4;
+    /* C3: b->j -> j->i -> i->a */
+    HE(m, tn2, NEXT) = (int32_t)t; HE(m, t, PREV) = (int32_t)tn2;
+    HE(m, t, NEXT) = (int32_t)tp1; HE(m, tp1, PREV) = (int32_t)t;
+    HE(m, t, FACE) = (int32_t)C3;
+}
+
+/* One T1 pass (Methods, "T1 transitions"): edges in ascending id, each with
+ * the current positions and topology.  For an edge shorter than l_min with
+ * midpoint mid = x_i + d/2 and direction u = d/l (u = (1,0) when l = 0):
+ *   stretch:  x_i = mid - (l_new/2) u,   x_j = mid + (l_new/2) u
+ *   exchange: x_i = mid + (l_new/2) n,   x_j = mid - (l_new/2) n,
+ *             n = (-u_y, u_x) the normal pointing into C1,
+ * with x_j written back in j's own image (minus offset(h) * L).  Both total
+ * energies are evaluated in full; the exchange is kept only if strictly
+ * lower. */
+int ora_t1_pass(ora_mesh *m, double *X, const ora_par *p, double l_min, double l_new,
+                int64_t *n_swap, int64_t *n_stretch)
+{
+    int64_t nv = m->n_vert, nhe = m->n_he;
+    int64_t n_e = nhe / 2;
+    int64_t *hoe = malloc(sizeof(int64_t) * (n_e + 1));
+    n_e = ora_edge_index(m, NULL, hoe);
+    double *XS = malloc(sizeof(double) * 2 * nv);
+    double *XT = malloc(sizeof(double) * 2 * nv);
+    int32_t *heT = malloc(sizeof(int32_t) * 8 * nhe);
+    int64_t sw = 0, st = 0;
+    for (int64_t e = 0; e < n_e; ++e) {
+        int64_t h = hoe[e];
+        double d[2];
+        edge_vec(m, X, h, d);
+        double l = sqrt(d[0] * d[0] + d[1] * d[1]);
+        if (!(l < l_min)) continue;
+        int64_t i = HE(m, h, SRC), j = HE(m, h, TGT);
+        double ox = HE(m, h, OX) * m->Lx, oy = HE(m, h, OY) * m->Ly;
+        double ux = 1.0, uy = 0.0;
+        if (l > 0.0) { ux = d[0] / l; uy = d[1] / l; }
+        double mx = X[2 * i] + 0.5 * d[0], my = X[2 * i + 1] + 0.5 * d[1];
+        double hl = 0.5 * l_new;
+        /* candidate S: stretch along u */
+        memcpy(XS, X, sizeof(double) * 2 * nv);
+        XS[2 * i] = mx - hl * ux;      XS[2 * i + 1] = my - hl * uy;
+        XS[2 * j] = mx + hl * ux - ox; XS[2 * j + 1] = my + hl * uy - oy;
+        double ES = ora_energy(m, XS, p);
+        /* candidate T: neighbour exchange */
+        int take_T = 0;
+        if (ora_t1_admissible(m, h)) {
+            ora_mesh mT = *m;
+            memcpy(heT, m->he, sizeof(int32_t) * 8 * nhe);
+            mT.he = heT;
+            ora_t1_topology(&mT, h);
+            double nx = -uy, ny = ux;
+            memcpy(XT, X, sizeof(double) * 2 * nv);
+            XT[2 * i] = mx + hl * nx;      XT[2 * i + 1] = my + hl * ny;
+            XT[2 * j] = mx - hl * nx - ox; XT[2 * j + 1] = my - hl * ny - oy;
+            double ET = ora_energy(&mT, XT, p);
+            take_T = ET < ES;
+        }
+        if (take_T) {
+            memcpy(m->he, heT, sizeof(int32_t) * 8 * nhe);
+            memcpy(X, XT, sizeof(double) * 2 * nv);
+            ++sw;
+        } else {
+            memcpy(X, XS, sizeof(double) * 2 * nv);
+            ++st;
+        }
+    }
+    free(hoe); free(XS); free(XT); free(heT);
+    if (n_swap) *n_swap = sw;
+    if (n_stretch) *n_stretch = st;
+    return 0;
+}
+
+/* ------------------------------------------------------------ relaxation */
+
+/* Nudge force -beta * P grad C, where P removes the per-component mean.
+ * The nudged energy E + beta C has its rigid-translation mode stiffened only
+ * by beta/N, so plain GD would crawl along it; with the mean removed the
+ * nudged equilibria are the same up to a rigid translation, and every EP
+ * estimate (lengths, perimeters) is translation invariant. */
+static void add_nudge(const ora_mesh *m, const double *X, const ora_relax_opts *o, double *F)
+{
+    if (o->beta == 0.0) return;
+    int64_t nv = m->n_vert;
+    double *g = malloc(sizeof(double) * 2 * nv);
+    if (o->X_target) {
+        ora_v2v(m, X, o->X_target, g);
+    } else if (o->g_lin) {
+        memcpy(g, o->g_lin, sizeof(double) * 2 * nv);
+    } else {
+        free(g);
+        return;
+    }
+    double sx = 0.0, sy = 0.0;
+    for (int64_t k = 0; k < nv; ++k) { sx += g[2 * k]; sy += g[2 * k + 1]; }
+    sx /= (double)nv; sy /= (double)nv;
+    for (int64_t k = 0; k < nv; ++k) {
+        F[2 * k] -= o->beta * (g[2 * k] - sx);
+        F[2 * k + 1] -= o->beta * (g[2 * k + 1] - sy);
+    }
+    free(g);
+}
+
+static double nudge_energy(const ora_mesh *m, const double *X, const ora_relax_opts *o)
+{
+    if (o->beta == 0.0) return 0.0;
+    if (o->X_target) return o->beta * ora_v2v(m, X, o->X_target, NULL);
+    if (o->g_lin) {
+        double s = 0.0;
+        for (int64_t k = 0; k < 2 * m->n_vert; ++k) s += o->g_lin[k] * X[k];
+        return o->beta * s;
+    }
+    return 0.0;
+}
+
+/* Gradient descent (Methods, "Simulation engine"); per iteration:
+ * T1 pass (if enabled), forces of E + beta*C, convergence test on the max
+ * force component with a patience counter, step X += eta F. */
+int ora_relax(ora_mesh *m, double *X, const ora_par *p, const ora_relax_opts *o, ora_relax_out *out)
+{
+    int64_t nv = m->n_vert;
+    double *F = malloc(sizeof(double) * 2 * nv);
+    int64_t count = 0, it = 0, n_t1 = 0, n_st = 0;
+    int32_t status = 1;
+    double mf = 0.0;
+    while (it < o->max_iter) {
+        if (o->t1_enable) {
+            int64_t a = 0, b = 0;
+            ora_t1_pass(m, X, p, o->l_min, o->l_new, &a, &b);
+            n_t1 += a; n_st += b;
+        }
+        ora_energy_forces(m, X, p, F);
+        add_nudge(m, X, o, F);
+        ++it;
+        mf = 0.0;
+        for (int64_t k = 0; k < 2 * nv; ++k) if (fabs(F[k]) > mf) mf = fabs(F[k]);
+        if (mf < o->tol) ++count; else count = 0;
+        if (count >= o->patience) { status = 0; break; }
+        for (int64_t k = 0; k < 2 * nv; ++k) X[k] += o->eta * F[k];
+    }
+    if (out) {
+        out->iters = it;
+        out->n_t1 = n_t1;
+        out->n_stretch = n_st;
+        out->max_f = mf;
+        out->energy = ora_energy(m, X, p) + nudge_energy(m, X, o);
+        out->status = status;
+    }
+    free(F);
+    return status;
+}
+
+/* ------------------------------------------------------------------- CG */
+
+static double dot(const double *a, const double *b, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+    return s;
+}
+
+static void project_zero_mean(double *v, int64_t nv)
+{
+    double sx = 0.0, sy = 0.0;
+    for (int64_t k = 0; k < nv; ++k) { sx += v[2 * k]; sy += v[2 * k + 1]; }
+    sx /= (double)nv; sy /= (double)nv;
+    for (int64_t k = 0; k < nv; ++k) { v[2 * k] -= sx; v[2 * k + 1] -= sy; }
+}
+
+/* Conjugate gradients on H mu = P b (P removes the per-component mean, the
+ * rigid-translation null space of a periodic tissue).  Starts from mu = 0;
+ * stops when |r| <= tol |P b| (status 0), when p^T H p <= 0 (status 2,
+ * negative curvature) or after maxit iterations (status 3).  The solution is
+ * projected to zero mean. */
+int ora_cg(const ora_mesh *m, const double *X, const ora_par *p, const double *b,
+           double tol, int64_t maxit, double *mu, int64_t *iters, double *rel_res)
+{
+    int64_t nv = m->n_vert, n = 2 * nv;
+    double *r = malloc(sizeof(double) * n);
+    double *q = malloc(sizeof(double) * n);
+    double *Aq = malloc(sizeof(double) * n);
+    memcpy(r, b, sizeof(double) * n);
+    project_zero_mean(r, nv);
+    double nb = sqrt(dot(r, r, n));
+    for (int64_t k = 0; k < n; ++k) { mu[k] = 0.0; q[k] = r[k]; }
+    double rr = dot(r, r, n);
+    int status = 3;
+    int64_t it = 0;
+    if (nb == 0.0) status = 0;
+    while (status == 3 && it < maxit) {
+        if (sqrt(rr) <= tol * nb) { status = 0; break; }
+        ora_hvp(m, X, p, q, Aq);
+        double qAq = dot(q, Aq, n);
+        if (!(qAq > 0.0)) { status = 2; break; }
+        double alpha = rr / qAq;
+        for (int64_t k = 0; k < n; ++k) { mu[k] += alpha * q[k]; r[k] -= alpha * Aq[k]; }
+        double rr_new = dot(r, r, n);
+        double beta = rr_new / rr;
+        for (int64_t k = 0; k < n; ++k) q[k] = r[k] + beta * q[k];
+        rr = rr_new;
+        ++it;
+    }
+    if (status == 3 && sqrt(rr) <= tol * nb) status = 0;
+    project_zero_mean(mu, nv);
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+    free(r); free(q); free(Aq);
+    return status;
+}

@@ -1,0 +1,203 @@
+"""Pins of the CPU oracle against closed forms, invariants and finite
+differences (no GPU).  Each test fixes a property that the paper's
+definitions or plain mathematics imply, so that a dropped term, a wrong sign
+or a transposed operand in the oracle fails at least one of them."""
+import numpy as np
+import pytest
+
+from paper_2604_06896_amd import tissue_gen as g
+
+
+def _rand_params(t, rng, lam_scale=0.1):
+    p = g.uniform_params(t)
+    p.KA = rng.uniform(0.5, 1.5, t.n_cell)
+    p.A0 = rng.uniform(0.8, 1.2, t.n_cell)
+    p.KP = rng.uniform(0.5, 1.5, t.n_cell)
+    p.P0 = rng.uniform(3.5, 4.0, t.n_cell)
+    p.lam = rng.uniform(0.0, 2 * lam_scale, t.n_edge)
+    return p
+
+
+@pytest.fixture(scope="module")
+def small():
+    rng = np.random.default_rng(7)
+    t = g.random_tissue(30, np.sqrt(30.0), rng=rng)
+    p = _rand_params(t, rng)
+    return t, p
+
+
+# ------------------------------------------------------------ geometry pins
+
+def test_hex_area_perimeter(oracle):
+    s = 0.62
+    t = g.hex_lattice(4, 6, s)
+    m = oracle.Mesh.from_tissue(t)
+    A, P, n = oracle.cells(m, t.X)
+    assert np.all(n == 6)
+    np.testing.assert_allclose(A, 1.5 * np.sqrt(3.0) * s * s, rtol=1e-12)
+    np.testing.assert_allclose(P, 6.0 * s, rtol=1e-12)
+    # shape index of a regular hexagon: P / sqrt(A) = sqrt(8 sqrt 3)
+    np.testing.assert_allclose(P / np.sqrt(A), np.sqrt(8 * np.sqrt(3.0)), rtol=1e-12)
+
+
+def test_hex_energy_closed_form(oracle):
+    s = 0.55
+    t = g.hex_lattice(4, 4, s)
+    KA, A0, KP, P0, lam = 1.3, 0.9, 0.7, 3.5, 0.2
+    p = g.uniform_params(t, KA=KA, A0=A0, KP=KP, P0=P0, lam=lam)
+    m = oracle.Mesh.from_tissue(t)
+    Ah, Ph = 1.5 * np.sqrt(3.0) * s * s, 6 * s
+    N = t.n_cell
+    expect = N * (KA * (Ah - A0) ** 2 + KP * (Ph - P0) ** 2) + 3 * N * lam * s
+    assert oracle.energy(m, t.X, p) == pytest.approx(expect, rel=1e-12)
+    E, F = oracle.energy_forces(m, t.X, p)
+    assert E == pytest.approx(expect, rel=1e-12)
+    # 3-fold symmetry of every vertex: the forces vanish for uniform parameters
+    assert np.abs(F).max() < 1e-12
+
+
+def test_tiling_identities(oracle, small):
+    t, _ = small
+    m = oracle.Mesh.from_tissue(t)
+    A, P, n = oracle.cells(m, t.X)
+    assert np.all(A > 0)
+    assert A.sum() == pytest.approx(t.Lx * t.Ly, rel=1e-12)
+    ell = oracle.edge_lengths(m, t.X)
+    assert P.sum() == pytest.approx(2 * ell.sum(), rel=1e-12)
+    # Euler on the torus: V - E + F = 0 with V = 2F, E = 3F
+    assert t.n_vert == 2 * t.n_cell and t.n_edge == 3 * t.n_cell
+    assert n.sum() == 6 * t.n_cell
+    # face closure of image offsets
+    for c in range(t.n_cell):
+        sel = t.he[:, 5] == c
+        assert t.he[sel, 6].sum() == 0 and t.he[sel, 7].sum() == 0
+
+
+def test_edge_index_rule(oracle, small):
+    t, _ = small
+    m = oracle.Mesh.from_tissue(t)
+    eoh, hoe = oracle.edge_index(m)
+    # the generator stores twins as (2e, 2e+1): the rule gives e = h // 2
+    np.testing.assert_array_equal(eoh, np.arange(t.n_he) // 2)
+    np.testing.assert_array_equal(hoe, 2 * np.arange(t.n_edge))
+
+
+def test_translation_invariance(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    E0, F0 = oracle.energy_forces(m, t.X, p)
+    E1, F1 = oracle.energy_forces(m, t.X + np.array([0.37, -1.21]), p)
+    assert E1 == pytest.approx(E0, rel=1e-12)
+    np.testing.assert_allclose(F1, F0, atol=1e-11)
+
+
+def test_rotation_by_90_degrees(oracle, small):
+    t, p = small
+    L = t.Lx
+    m = oracle.Mesh.from_tissue(t)
+    E0, F0 = oracle.energy_forces(m, t.X, p)
+    # rotate (x, y) -> (-y, x); image offsets rotate the same way
+    Xr = np.stack([-t.X[:, 1], t.X[:, 0]], 1)
+    he = t.he.copy()
+    he[:, 6], he[:, 7] = -t.he[:, 7], t.he[:, 6]
+    mr = oracle.Mesh(he, t.n_vert, L, L)
+    E1, F1 = oracle.energy_forces(mr, Xr, p)
+    assert E1 == pytest.approx(E0, rel=1e-12)
+    np.testing.assert_allclose(F1, np.stack([-F0[:, 1], F0[:, 0]], 1), atol=1e-11)
+
+
+# ------------------------------------------------------------- force pins
+
+def test_forces_match_central_differences(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    rng = np.random.default_rng(3)
+    X = t.X + rng.normal(0, 0.03, t.X.shape)
+    E, F = oracle.energy_forces(m, X, p)
+    assert E == pytest.approx(oracle.energy(m, X, p), rel=1e-14)
+    h = 1e-6
+    Ffd = np.empty_like(X)
+    for k in range(t.n_vert):
+        for c in range(2):
+            Xp = X.copy(); Xp[k, c] += h
+            Xm = X.copy(); Xm[k, c] -= h
+            Ffd[k, c] = -(oracle.energy(m, Xp, p) - oracle.energy(m, Xm, p)) / (2 * h)
+    assert np.abs(F - Ffd).max() < 1e-6 * np.abs(F).max()
+
+
+def test_net_force_and_torque_free(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    _, F = oracle.energy_forces(m, t.X, p)
+    assert np.abs(F.sum(0)).max() < 1e-11 * np.abs(F).max() * t.n_vert
+
+
+def test_energy_decreases_along_force(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    E0, F = oracle.energy_forces(m, t.X, p)
+    E1 = oracle.energy(m, t.X + 1e-5 * F, p)
+    # first-order decrease: E1 - E0 = -1e-5 |F|^2 + O(1e-10)
+    assert E1 - E0 == pytest.approx(-1e-5 * (F * F).sum(), rel=1e-3)
+
+
+# --------------------------------------------------------------- HVP pins
+
+def test_hvp_matches_force_differences(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    rng = np.random.default_rng(4)
+    X = t.X + rng.normal(0, 0.02, t.X.shape)
+    v = rng.normal(size=X.shape)
+    Hv = oracle.hvp(m, X, p, v)
+    h = 1e-5
+    _, Fp = oracle.energy_forces(m, X + h * v, p)
+    _, Fm = oracle.energy_forces(m, X - h * v, p)
+    Hv_fd = -(Fp - Fm) / (2 * h)
+    assert np.abs(Hv - Hv_fd).max() < 1e-6 * np.abs(Hv).max()
+
+
+def test_hvp_symmetric_and_translation_null(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=t.X.shape)
+    v = rng.normal(size=t.X.shape)
+    a = (u * oracle.hvp(m, t.X, p, v)).sum()
+    b = (v * oracle.hvp(m, t.X, p, u)).sum()
+    assert a == pytest.approx(b, rel=1e-11)
+    for d in ([1.0, 0.0], [0.0, 1.0]):
+        Hd = oracle.hvp(m, t.X, p, np.tile(d, (t.n_vert, 1)))
+        assert np.abs(Hd).max() < 1e-11
+
+
+def test_mixed_derivatives_match_differences(oracle, small):
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    rng = np.random.default_rng(6)
+    mu = rng.normal(size=t.X.shape)
+    h = 1e-6
+    # lambda: (d2E/dX dlambda_e) . mu = d/dh l_e(X + h mu)
+    ml = oracle.mixed_lambda(m, t.X, mu)
+    lp = oracle.edge_lengths(m, t.X + h * mu)
+    lm = oracle.edge_lengths(m, t.X - h * mu)
+    np.testing.assert_allclose(ml, (lp - lm) / (2 * h), atol=1e-7)
+    # P0: dE/dP0_c = -2 KP (P_c - P0_c)  ->  mixed = -2 KP d/dh P_c(X + h mu)
+    mp = oracle.mixed_p0(m, t.X, p, mu)
+    _, Pp, _ = oracle.cells(m, t.X + h * mu)
+    _, Pm, _ = oracle.cells(m, t.X - h * mu)
+    np.testing.assert_allclose(mp, -2 * p.KP * (Pp - Pm) / (2 * h), atol=1e-7)
+
+
+# ---------------------------------------------------------------- v2v pins
+
+def test_v2v_closed_form_and_min_image(oracle, small):
+    t, _ = small
+    m = oracle.Mesh.from_tissue(t)
+    c = np.array([0.3, -0.4])
+    C0, gC = oracle.v2v(m, t.X + c, t.X)
+    assert C0 == pytest.approx(0.5 * (c * c).sum(), rel=1e-12)
+    np.testing.assert_allclose(gC, np.tile(c / t.n_vert, (t.n_vert, 1)), rtol=1e-12)
+    # a whole-box shift is the same periodic configuration
+    C1, _ = oracle.v2v(m, t.X + c + np.array([t.Lx, -t.Ly]), t.X)
+    assert C1 == pytest.approx(C0, rel=1e-9)
