@@ -1,0 +1,260 @@
+/*
+ * vtx.h -- C ABI of an MI355X (gfx950) library for the periodic 2-D vertex
+ * model of confluent epithelia described in VertAX (arXiv 2604.06896).
+ *
+ * The library evaluates the energy
+ *
+ *     E(X, theta) = sum_cells [ K_A (A - A0)^2 + K_P (P - P0)^2 ]
+ *                 + sum_edges lambda * l
+ *
+ * (Methods, "Vertex model formulation": equation E1 with the line-tension
+ * term of equation E2) and its per-vertex forces F = -grad_X E, relaxes a
+ * tissue to mechanical equilibrium by gradient descent with T1 neighbour
+ * exchanges (Methods, "Simulation engine" and "T1 transitions"), and
+ * returns the gradient of an outer cost with respect to the mechanical
+ * parameters at that equilibrium (Methods, "Gradient computation methods":
+ * implicit differentiation in adjoint form, and centred equilibrium
+ * propagation).
+ *
+ * Conventions shared by every call
+ *  - Topology is the paper's half-edge table (Methods, "System state and
+ *    data structure"): int32 [n_he][8] with columns prev, next, twin,
+ *    source, target, face, x-offset, y-offset.  The offsets (each -1, 0 or
+ *    +1) give the periodic image of the target, so the edge vector of
+ *    half-edge h is X[tgt] + (ox*Lx, oy*Ly) - X[src].  Faces are traversed
+ *    counter-clockwise (a cell lies left of its half-edges); vertices are
+ *    3-valent.
+ *  - Edges are numbered 0..n_edge-1 in ascending order of the lower
+ *    half-edge id of each twin pair; lambda and edge gradients use this
+ *    numbering.
+ *  - X (vertex positions) and F (forces) are device arrays [n_vert][2]
+ *    (x, y interleaved).  Their element type is set by the precision mode:
+ *      VTX_F32    float  X and F, float arithmetic;
+ *      VTX_F64    double X and F, double arithmetic;
+ *      VTX_MIXED  double X and F; local coordinate differences are rounded
+ *                 to float and the force arithmetic is float.
+ *    In every mode energy totals, the max-force convergence test, CG dot
+ *    products, step sizes and T1 decisions are computed in double.
+ *  - Parameter arrays (vtx_params) are device arrays with the element type
+ *    of X; a NULL array means "use the scalar field".
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Calls that return results through device pointers are asynchronous in
+ *    stream order and allocate nothing, so they can be captured in a HIP
+ *    graph.  Calls that return results through host pointers synchronise
+ *    the stream.
+ *  - Every call returns VTX_OK (0) or a negative error code; the message of
+ *    the last error of the calling thread is returned by vtx_last_error().
+ *    Memory is owned by the caller except for tissue and batch handles,
+ *    which own their topology and all workspaces (allocated at creation).
+ */
+#ifndef VTX_H
+#define VTX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes (negative) */
+#define VTX_OK 0
+#define VTX_E_ARG (-1)        /* invalid argument (null pointer, size, mode) */
+#define VTX_E_TOPOLOGY (-2)   /* half-edge table is not a valid periodic 3-valent tiling */
+#define VTX_E_CAPACITY (-3)   /* a size exceeds a library limit */
+#define VTX_E_HIP (-4)        /* HIP runtime error */
+#define VTX_E_NONFINITE (-5)  /* a NaN or infinity appeared in the forces */
+
+/* statuses (reported in result structs; not errors) */
+#define VTX_CONVERGED 0
+#define VTX_NOT_CONVERGED 1
+#define VTX_CG_NEG_CURVATURE 2
+#define VTX_CG_MAXITER 3
+
+/* precision modes */
+#define VTX_F32 0
+#define VTX_F64 1
+#define VTX_MIXED 2
+
+/* parameter selectors */
+#define VTX_THETA_LAMBDA 0   /* theta = per-edge line tensions lambda_e   */
+#define VTX_THETA_P0 1       /* theta = per-cell preferred perimeters P0_c */
+
+/* hypergradient estimators */
+#define VTX_GRAD_ADJOINT 0     /* implicit differentiation, adjoint form, CG */
+#define VTX_GRAD_EP_CENTRED 1  /* centred equilibrium propagation            */
+
+typedef struct vtx_tissue_s *vtx_tissue;
+typedef struct vtx_batch_s *vtx_batch;
+
+/* Mechanical parameters: per-cell K_A, A0, K_P, P0 and per-edge lambda
+ * (Methods, "Vertex model formulation"; parameters may be heterogeneous,
+ * Results, "Energy functions"). */
+typedef struct {
+    const void *KA, *A0, *KP, *P0;  /* device [n_cell] or NULL */
+    const void *lam;                /* device [n_edge] or NULL */
+    double KA_s, A0_s, KP_s, P0_s, lam_s;
+} vtx_params;
+
+/* Gradient-descent options (Methods, "Simulation engine").
+ *   X <- X + eta * F,  stop when max_k |F_k| < tol on `patience`
+ *   consecutive iterations (max over all 2*n_vert components) or after
+ *   max_iter force evaluations.  One iteration is: T1 pass (if enabled),
+ *   forces, convergence test, step.
+ * T1 (Methods, "T1 transitions"): every iteration, edges with length
+ *   l < l_min are visited in ascending edge id; each is either stretched to
+ *   length l_new along its direction or exchanged for an orthogonal edge of
+ *   length l_new through the same midpoint, whichever gives the strictly
+ *   lower total energy (ties keep the stretch); the exchange is not
+ *   considered if a cell losing the edge is a triangle or the four cells
+ *   around it are not distinct.
+ * Nudge (Methods, "Equilibrium propagation"): if beta != 0 the relaxed
+ *   energy is E + beta*C with C the v2v cost to X_target (device, same
+ *   element type as X) or, if X_target is NULL, the linear cost g_lin . X
+ *   (g_lin: double device array [n_vert][2]).
+ *   The mean of grad C over the vertices is removed from the nudge force
+ *   (rigid translations do not change any EP estimate and are otherwise
+ *   stiffened only by beta/n_vert).  A nudge cannot be combined with T1. */
+typedef struct {
+    double eta, tol;
+    int64_t patience, max_iter;
+    int32_t t1_enable;
+    double l_min, l_new;
+    double beta;
+    const void *X_target;
+    const void *g_lin;
+    int32_t chunk;   /* iterations per captured graph launch (0 = 256) */
+} vtx_relax_opts;
+
+typedef struct {
+    int64_t iters;      /* force evaluations performed */
+    int64_t n_t1;       /* accepted neighbour exchanges */
+    int64_t n_stretch;  /* short edges stretched instead */
+    double max_f;       /* max |F| component of the last evaluation */
+    double energy;      /* E (+ beta*C) at the returned positions */
+    int32_t status;     /* VTX_CONVERGED or VTX_NOT_CONVERGED */
+} vtx_relax_result;
+
+typedef struct {
+    int32_t method;        /* VTX_GRAD_ADJOINT or VTX_GRAD_EP_CENTRED */
+    int32_t theta;         /* VTX_THETA_LAMBDA or VTX_THETA_P0 */
+    double cg_tol;         /* relative residual |r| / |P b| */
+    int64_t cg_max_iter;
+    double beta;           /* EP nudge (relaxations at +-beta/2) */
+    vtx_relax_opts ep_relax; /* EP relaxation options (beta fields ignored) */
+} vtx_grad_opts;
+
+typedef struct {
+    int64_t cg_iters;
+    double cg_rel_res;     /* recursive relative residual at exit */
+    int32_t status;        /* VTX_CONVERGED, VTX_CG_NEG_CURVATURE, VTX_CG_MAXITER,
+                              or for EP the worse of the two relaxation statuses */
+    vtx_relax_result ep_plus, ep_minus;
+} vtx_grad_result;
+
+/* ------------------------------------------------------------ tissues */
+
+/* Create a tissue handle from a host half-edge table.  Validates the table
+ * (twin involution with reversed ends and negated offsets, prev/next
+ * inverse, source(next(h)) = target(h), faces of >= 3 sides whose offsets
+ * sum to zero, 3-valent vertices, offsets in {-1,0,1}, no edge from a
+ * vertex to its own image) and stages the device layouts: cell->corner
+ * rows, vertex stars and the edge list.  The caller keeps ownership of
+ * `he`.  Errors: VTX_E_ARG, VTX_E_TOPOLOGY, VTX_E_CAPACITY (n_vert >= 2^28,
+ * a cell spanning more than one periodic image), VTX_E_HIP. */
+int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n_cell,
+                      double Lx, double Ly, vtx_tissue *out);
+int vtx_tissue_destroy(vtx_tissue t);
+/* Sizes of a tissue (any pointer may be NULL). */
+int vtx_tissue_sizes(vtx_tissue t, int64_t *n_vert, int64_t *n_cell, int64_t *n_edge,
+                     int64_t *n_he);
+/* Copy the current half-edge table (it changes under T1) to host memory
+ * [n_he][8].  Synchronises the device. */
+int vtx_tissue_get_topology(vtx_tissue t, int32_t *he_out);
+/* Replace the topology by a host table of the same sizes (validated as at
+ * creation). */
+int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he);
+
+/* Energy and forces at X (Methods, "Vertex model formulation").
+ * E_dev: device double scalar or NULL; F: device [n_vert][2] or NULL;
+ * maxf_dev: device double scalar (max |F| component) or NULL.
+ * Asynchronous; graph-capturable. */
+int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                      double *E_dev, void *F, double *maxf_dev, void *stream);
+
+/* Per-cell area and perimeter at X (double device arrays [n_cell], either
+ * may be NULL).  Asynchronous. */
+int vtx_cell_geometry(vtx_tissue t, int32_t mode, const void *X, double *A_dev,
+                      double *P_dev, void *stream);
+
+/* Per-edge lengths at X (double device array [n_edge]).  Asynchronous. */
+int vtx_edge_lengths(vtx_tissue t, int32_t mode, const void *X, double *len_dev,
+                     void *stream);
+
+/* Relax X in place to mechanical equilibrium (Methods, "Simulation
+ * engine").  The loop runs on the device in captured graphs of `chunk`
+ * iterations; the host reads an 8-byte status between chunks.  T1 mutates
+ * the tissue's topology.  `res` is a host struct; synchronises. */
+int vtx_relax(vtx_tissue t, int32_t mode, void *X, const vtx_params *p,
+              const vtx_relax_opts *o, vtx_relax_result *res, void *stream);
+
+/* One T1 pass over X (Methods, "T1 transitions"), with the rules of
+ * vtx_relax_opts.  Mutates X and the topology; counts are returned in host
+ * memory (either may be NULL); synchronises. */
+int vtx_t1(vtx_tissue t, int32_t mode, void *X, const vtx_params *p, double l_min,
+           double l_new, int64_t *n_swap, int64_t *n_stretch, void *stream);
+
+/* Hessian-vector product H v at X (H = d2E/dX2); v and Hv are double device
+ * arrays [n_vert][2].  Asynchronous. */
+int vtx_hvp(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p, const double *v,
+            double *Hv, void *stream);
+
+/* Gradient of an outer cost C with respect to theta at the equilibrium
+ * X_star (Methods, "Implicit differentiation (ID)" and "Equilibrium
+ * propagation (EP)").
+ *   ADJOINT: solves H mu = P dC_dX by CG on the zero-mean subspace
+ *     (P removes the per-component mean; rigid translations are null
+ *     vectors of H) and returns  dC_dtheta = -(d2E/dX dtheta)^T mu.
+ *     dC_dX is a double device array [n_vert][2] (the backward of any cost).
+ *   EP_CENTRED: relaxes E + (beta/2) C and E - (beta/2) C from X_star and
+ *     returns (dE/dtheta(X+) - dE/dtheta(X-)) / beta, where C is the v2v
+ *     cost to X_target when given (device, element type of X) and the
+ *     linear cost dC_dX . X otherwise.
+ * The explicit partial d_theta C is not added (zero for costs of X only).
+ * dC_dtheta: double device array [n_edge] (lambda) or [n_cell] (P0).
+ * `res` is a host struct; synchronises. */
+int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_params *p,
+                   const double *dC_dX, const void *X_target, const vtx_grad_opts *o,
+                   double *dC_dtheta, vtx_grad_result *res, void *stream);
+
+/* v2v cost C = 1/(2 n_vert) sum_k |x_k - x_target,k|^2 (minimum periodic
+ * image; Methods, "Geometric vertex-to-vertex (v2v) cost") and its gradient
+ * (x_k - x_target,k)/n_vert.  C_dev: device double scalar or NULL; grad:
+ * double device [n_vert][2] or NULL.  Asynchronous. */
+int vtx_v2v(vtx_tissue t, int32_t mode, const void *X, const void *X_target, double *C_dev,
+            double *grad, void *stream);
+
+/* ------------------------------------------------------------- batches */
+
+/* Group independent tissues for batched relaxation.  The handles stay
+ * owned by the caller and must outlive the batch. */
+int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out);
+int vtx_batch_destroy(vtx_batch b);
+
+/* Relax every tissue of the batch (each with its own X, parameters and the
+ * shared options) in one persistent launch: one workgroup per tissue
+ * (schedule 0) or `blocks_per_tissue` cooperating workgroups (schedule 1),
+ * tissues taken from a device work queue in descending size.  X and p are
+ * host arrays of n entries (device pointers inside).  Results go to the
+ * host array res[n]; synchronises.  Nudges are not supported here. */
+int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
+                    const vtx_relax_opts *o, int32_t schedule, int32_t block_threads,
+                    vtx_relax_result *res, void *stream);
+
+/* Message of the last error on the calling thread (never NULL). */
+const char *vtx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VTX_H */

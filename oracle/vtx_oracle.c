@@ -49,7 +49,9 @@
  *     null vectors; the adjoint system is solved on the zero-mean subspace
  *     (right-hand side projected, solution projected);
  *   - the v2v displacement uses the minimum periodic image;
- *   - the EP nudge force has its mean removed (see add_nudge).
+ *   - the EP nudge force has its mean removed (see add_nudge);
+ *   - at a zero-length edge the gradient of its length is taken as zero
+ *     (the minimum-norm subgradient; see unit()).
  */
 #include <math.h>
 #include <stdint.h>
@@ -125,6 +127,10 @@ void ora_edge_lengths(const ora_mesh *m, const double *X, double *len)
     }
     free(hoe);
 }
+
+/* d / l, the gradient of an edge length; at a zero-length edge the length
+ * is not differentiable and the minimum-norm subgradient, zero, is used. */
+static double unit(double a, double l) { return l > 0.0 ? a / l : 0.0; }
 
 /* First (lowest-id) half-edge of every cell. */
 static void first_half_edges(const ora_mesh *m, int64_t *first)
@@ -218,10 +224,10 @@ double ora_energy_forces(const ora_mesh *m, const double *X, const ora_par *p, d
             g[2 * s + 1] += cA * 0.5 * (-ax);
             /* perimeter through this edge */
             double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-            g[2 * s] -= cP * d[0] / l;
-            g[2 * s + 1] -= cP * d[1] / l;
-            g[2 * t] += cP * d[0] / l;
-            g[2 * t + 1] += cP * d[1] / l;
+            g[2 * s] -= cP * unit(d[0], l);
+            g[2 * s + 1] -= cP * unit(d[1], l);
+            g[2 * t] += cP * unit(d[0], l);
+            g[2 * t + 1] += cP * unit(d[1], l);
             h = HE(m, h, NEXT);
         } while (h != first[c]);
     }
@@ -235,10 +241,10 @@ double ora_energy_forces(const ora_mesh *m, const double *X, const ora_par *p, d
         double l = sqrt(d[0] * d[0] + d[1] * d[1]);
         int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
         E += p->lam[e] * l;
-        g[2 * s] -= p->lam[e] * d[0] / l;
-        g[2 * s + 1] -= p->lam[e] * d[1] / l;
-        g[2 * t] += p->lam[e] * d[0] / l;
-        g[2 * t + 1] += p->lam[e] * d[1] / l;
+        g[2 * s] -= p->lam[e] * unit(d[0], l);
+        g[2 * s + 1] -= p->lam[e] * unit(d[1], l);
+        g[2 * t] += p->lam[e] * unit(d[0], l);
+        g[2 * t + 1] += p->lam[e] * unit(d[1], l);
     }
     if (F)
         for (int64_t k = 0; k < 2 * nv; ++k) F[k] = -g[k];
@@ -277,7 +283,7 @@ void ora_hvp(const ora_mesh *m, const double *X, const ora_par *p, const double 
             double ax = d[0] + dprev[0], ay = d[1] + dprev[1];
             dA += 0.5 * ay * v[2 * s] + 0.5 * (-ax) * v[2 * s + 1];
             double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-            dP += (d[0] * (v[2 * t] - v[2 * s]) + d[1] * (v[2 * t + 1] - v[2 * s + 1])) / l;
+            dP += unit(d[0], l) * (v[2 * t] - v[2 * s]) + unit(d[1], l) * (v[2 * t + 1] - v[2 * s + 1]);
             h = HE(m, h, NEXT);
         } while (h != first[c]);
         /* second pass: assemble */
@@ -296,10 +302,10 @@ void ora_hvp(const ora_mesh *m, const double *X, const ora_par *p, const double 
             Hv[2 * s + 1] += 2.0 * p->KA[c] * dA * gAy + cA * 0.5 * (-wx);
             /* perimeter through this edge: grad l = -u at s, +u at t */
             double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-            double ux = d[0] / l, uy = d[1] / l;
+            double ux = unit(d[0], l), uy = unit(d[1], l);
             double rx = v[2 * t] - v[2 * s], ry = v[2 * t + 1] - v[2 * s + 1];
             double ru = rx * ux + ry * uy;
-            double dux = (rx - ru * ux) / l, duy = (ry - ru * uy) / l;
+            double dux = unit(rx - ru * ux, l), duy = unit(ry - ru * uy, l);
             Hv[2 * s] += 2.0 * p->KP[c] * dP * (-ux) + cP * (-dux);
             Hv[2 * s + 1] += 2.0 * p->KP[c] * dP * (-uy) + cP * (-duy);
             Hv[2 * t] += 2.0 * p->KP[c] * dP * ux + cP * dux;
@@ -316,10 +322,10 @@ void ora_hvp(const ora_mesh *m, const double *X, const ora_par *p, const double 
         edge_vec(m, X, h, d);
         int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
         double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-        double ux = d[0] / l, uy = d[1] / l;
+        double ux = unit(d[0], l), uy = unit(d[1], l);
         double rx = v[2 * t] - v[2 * s], ry = v[2 * t + 1] - v[2 * s + 1];
         double ru = rx * ux + ry * uy;
-        double dux = (rx - ru * ux) / l, duy = (ry - ru * uy) / l;
+        double dux = unit(rx - ru * ux, l), duy = unit(ry - ru * uy, l);
         Hv[2 * s] -= p->lam[e] * dux;
         Hv[2 * s + 1] -= p->lam[e] * duy;
         Hv[2 * t] += p->lam[e] * dux;
@@ -342,7 +348,7 @@ void ora_mixed_lambda(const ora_mesh *m, const double *X, const double *mu, doub
         edge_vec(m, X, h, d);
         int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
         double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-        out[e] = (d[0] * (mu[2 * t] - mu[2 * s]) + d[1] * (mu[2 * t + 1] - mu[2 * s + 1])) / l;
+        out[e] = unit(d[0], l) * (mu[2 * t] - mu[2 * s]) + unit(d[1], l) * (mu[2 * t + 1] - mu[2 * s + 1]);
     }
     free(hoe);
 }
@@ -360,7 +366,7 @@ void ora_mixed_p0(const ora_mesh *m, const double *X, const ora_par *p, const do
             edge_vec(m, X, h, d);
             int64_t s = HE(m, h, SRC), t = HE(m, h, TGT);
             double l = sqrt(d[0] * d[0] + d[1] * d[1]);
-            dP += (d[0] * (mu[2 * t] - mu[2 * s]) + d[1] * (mu[2 * t + 1] - mu[2 * s + 1])) / l;
+            dP += unit(d[0], l) * (mu[2 * t] - mu[2 * s]) + unit(d[1], l) * (mu[2 * t + 1] - mu[2 * s + 1]);
             h = HE(m, h, NEXT);
         } while (h != first[c]);
         out[c] = -2.0 * p->KP[c] * dP;

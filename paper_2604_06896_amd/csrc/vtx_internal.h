@@ -1,0 +1,177 @@
+// Internal declarations shared by the HIP sources of libvtx (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vtx.h"
+
+namespace vtx {
+
+// ------------------------------------------------------------------ packing
+// Vertex ids carry a 4-bit periodic image code in their top bits:
+// bits 28-29 hold (ox + 1), bits 30-31 hold (oy + 1).
+constexpr int kIdBits = 28;
+constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
+constexpr int kBlock = 256;          // threads per block of the grid kernels
+constexpr int kRowLds = 16 * kBlock; // corner ints staged in LDS per cell block
+constexpr int kT1SortCap = 4096;     // T1 candidates sorted in LDS
+constexpr int kT1Extra = 256;        // pending re-checks during one T1 pass
+
+__host__ __device__ inline int32_t pack_id(int32_t id, int ox, int oy) {
+    return (int32_t)((uint32_t)id | ((uint32_t)((ox + 1) | ((oy + 1) << 2)) << kIdBits));
+}
+__host__ __device__ inline int32_t id_of(int32_t w) { return (int32_t)((uint32_t)w & kIdMask); }
+__host__ __device__ inline int ox_of(int32_t w) { return (int)(((uint32_t)w >> kIdBits) & 3u) - 1; }
+__host__ __device__ inline int oy_of(int32_t w) {
+    return (int)(((uint32_t)w >> (kIdBits + 2)) & 3u) - 1;
+}
+
+enum { HP = 0, HN, HT, HS, HG, HF, HOX, HOY };  // half-edge table columns
+
+// ------------------------------------------------------- device structures
+struct DevTissue {
+    int32_t n_vert, n_cell, n_edge, n_he;
+    double Lx, Ly;
+    int32_t *he;         // [n_he][8] current topology
+    int32_t *he_edge;    // [n_he] edge id of each half-edge
+    int32_t *edge_he;    // [n_edge] lower half-edge of each edge
+    int32_t *row_ptr;    // [n_cell + 1] cell -> corner rows
+    int32_t *corner;     // [n_he] packed vertex id + image relative to corner 0
+    int32_t *corner_he;  // [n_he] half-edge leaving each corner
+    int32_t *nsides;     // [n_cell]
+    int32_t *cell_he;    // [n_cell] one half-edge of each cell
+    int32_t *star_nb;    // [3][n_vert] packed neighbour id + image
+    int32_t *star_cell;  // [3][n_vert] sector cell k lies between neighbours k and k+1
+    int32_t *star_edge;  // [3][n_vert]
+    int32_t *star_he;    // [3][n_vert] outgoing half-edges, counter-clockwise
+};
+
+template <typename P>
+struct DevParams {
+    const P *KA, *A0, *KP, *P0, *lam;
+    P KA_s, A0_s, KP_s, P0_s, lam_s;
+    __device__ __forceinline__ P ka(int c) const { return KA ? KA[c] : KA_s; }
+    __device__ __forceinline__ P a0(int c) const { return A0 ? A0[c] : A0_s; }
+    __device__ __forceinline__ P kp(int c) const { return KP ? KP[c] : KP_s; }
+    __device__ __forceinline__ P p0(int c) const { return P0 ? P0[c] : P0_s; }
+    __device__ __forceinline__ P lm(int e) const { return lam ? lam[e] : lam_s; }
+};
+
+// Device control block of an iterative loop (relaxation or CG).  Only the
+// library's kernels touch it; the host reads it between graph launches.
+struct LoopCtl {
+    unsigned long long maxf_bits;  // running max |F| (double bits, >= 0)
+    unsigned int arrive;           // blocks of the current launch that finished
+    unsigned int arrive2;
+    int32_t done;
+    int32_t status;
+    int32_t result_buf;            // 0: caller's X, 1: library buffer
+    int32_t topo_changed;
+    int64_t iter;
+    int64_t max_iter, patience, count;
+    double tol;
+    double last_maxf;
+    int64_t n_t1, n_stretch;
+    uint32_t t1_count;             // candidates appended in the current pass
+    int32_t t1_overflow;
+    double nudge_mean[2];
+    // CG scalars
+    double rr, rr0, pAp, alpha, beta_cg, rel_res;
+    int64_t cg_iter;
+};
+
+struct Workspace {
+    void *xbuf;          // second position buffer (double [n_vert][2])
+    double *cap;         // per-cell (cA, cP) in the arithmetic type, sized for double
+    double *cell_aux;    // per-cell auxiliaries (HVP: dA, dP), double [n_cell][2]
+    double *partials;    // per-block partial sums (double)
+    double *partials2;
+    int32_t *t1_list;    // [n_edge] candidate corner indices
+    LoopCtl *ctl;        // device control block
+    LoopCtl *ctl_host;   // pinned host mirror
+    double *cg;          // CG vectors: x, r, p, Ap (double [4][n_vert][2])
+    double *scal;        // device scalars
+    hipStream_t cap_stream;
+};
+
+// ------------------------------------------------------ small device maths
+// xa + w*L - xb with the periodic shift applied exactly: the operand next to
+// the box face is moved by L first (exact by Sterbenz's lemma when it lies
+// within [L/2, 2L]), then two nearby values are subtracted.
+template <typename T>
+__host__ __device__ __forceinline__ T pdiff(T xa, T xb, int w, T L) {
+    if (w > 0) return xa - (xb - L);
+    if (w < 0) return (xa - L) - xb;
+    return xa - xb;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) {
+    return d - L * floor(d / L + 0.5);
+}
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ typename Vec2<T>::type ld2(const T *p, int64_t i) {
+    return reinterpret_cast<const typename Vec2<T>::type *>(p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *p, int64_t i, T x, T y) {
+    typename Vec2<T>::type v;
+    v.x = x;
+    v.y = y;
+    reinterpret_cast<typename Vec2<T>::type *>(p)[i] = v;
+}
+
+// Block-wide sum of a double (fixed order: deterministic for a fixed block size).
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r += sh[w];
+    }
+    return r;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r = fmax(r, sh[w]);
+    }
+    return r;
+}
+
+__device__ __forceinline__ double ld_acquire(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by thread 0 after the block's results are stored: returns true in
+// exactly one block (the last to arrive), which then sees every block's
+// stores.  The counter is reset by that block.
+__device__ __forceinline__ bool last_block(unsigned int *counter) {
+    __threadfence();
+    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    bool last = prev == gridDim.x - 1;
+    if (last) {
+        __threadfence();
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return last;
+}
+
+}  // namespace vtx

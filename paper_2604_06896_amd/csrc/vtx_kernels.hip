@@ -1,0 +1,924 @@
+// HIP kernels of libvtx for gfx950 (wave64) and their launchers.
+//
+// Hot path per energy/force evaluation (VertAX, arXiv 2604.06896, Methods,
+// "Vertex model formulation"):
+//   k_cell    one lane per cell: corner rows staged through LDS, shoelace
+//             area and perimeter in a cell-local frame, cA = 2K_A(A-A0),
+//             cP = 2K_P(P-P0), FP64 energy partial per block;
+//   k_vertex  one lane per 3-valent vertex: gathers its 3 neighbours, 3 cells
+//             and 3 edge tensions and forms F with no atomics; the max |F|
+//             and energy are reduced per block and finished by the last block
+//             (fixed order, deterministic).  In relaxation it also takes the
+//             gradient-descent step and runs the convergence test on the
+//             device (Methods, "Simulation engine").
+//   k_t1      one workgroup: sequential T1 pass over the short edges flagged
+//             by k_cell (Methods, "T1 transitions").
+// Adjoint (Methods, "Implicit differentiation (ID)"): k_hvp_cell/k_hvp_vertex
+// form H v with the same gathers, k_cg_* run conjugate gradients with FP64
+// dots and device-side scalars, k_contract_* apply the mixed derivatives.
+#include <climits>
+
+#include "vtx_device.h"
+#include "vtx_launch.h"
+
+namespace vtx {
+
+enum { F_ENERGY = 1, F_T1DET = 2, F_NUDGE_V2V = 4 };
+
+// ------------------------------------------------------------------ cells
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__restrict__ X,
+                                                 DevParams<PosT> p, M *__restrict__ cap,
+                                                 double *__restrict__ epart, LoopCtl *ctl,
+                                                 int32_t *t1_list, M lmin2, int flags,
+                                                 const PosT *__restrict__ Xt,
+                                                 double *__restrict__ npart) {
+    if (ctl->done) return;
+    __shared__ int32_t rows[kRowLds];
+    __shared__ double sh[kBlock / 64];
+    const int nc = t.n_cell;
+    const int c0 = blockIdx.x * kBlock;
+    const int c = c0 + threadIdx.x;
+    const int cend = min(c0 + kBlock, nc);
+    const int base = t.row_ptr[c0], top = t.row_ptr[cend];
+    const bool staged = top - base <= kRowLds;
+    if (staged)
+        for (int i = threadIdx.x; i < top - base; i += kBlock) rows[i] = t.corner[base + i];
+    __syncthreads();
+    const bool det = (flags & F_T1DET) != 0;
+    double e = 0.0;
+    if (c < nc) {
+        const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+        M A, P;
+        if (staged)
+            cell_geom<PosT, M>(
+                t, X, n, [&](int k) { return rows[rb - base + k]; }, rb, A, P, det, lmin2,
+                t1_list, &ctl->t1_count);
+        else
+            cell_geom<PosT, M>(
+                t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, det, lmin2,
+                t1_list, &ctl->t1_count);
+        const M ka = (M)p.ka(c), kp = (M)p.kp(c);
+        const M da = A - (M)p.a0(c), dp = P - (M)p.p0(c);
+        st2(cap, c, (M)2 * ka * da, (M)2 * kp * dp);
+        if (flags & F_ENERGY)
+            e = (double)ka * (double)da * (double)da + (double)kp * (double)dp * (double)dp;
+    }
+    if (flags & F_ENERGY) {
+        const double s = block_sum(e, sh);
+        if (threadIdx.x == 0) epart[blockIdx.x] = s;
+    }
+    if (flags & F_NUDGE_V2V) {
+        // mean over vertices of the v2v displacement (minimum image)
+        double sx = 0.0, sy = 0.0;
+        for (int v = blockIdx.x * kBlock + threadIdx.x; v < t.n_vert; v += gridDim.x * kBlock) {
+            sx += min_image((double)X[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
+            sy += min_image((double)X[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
+        }
+        const double bx = block_sum(sx, sh);
+        const double by = block_sum(sy, sh);
+        if (threadIdx.x == 0) {
+            npart[2 * blockIdx.x] = bx;
+            npart[2 * blockIdx.x + 1] = by;
+            if (last_block(&ctl->arrive2)) {
+                double ax = 0.0, ay = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) {
+                    ax += ld_acquire(npart + 2 * b);
+                    ay += ld_acquire(npart + 2 * b + 1);
+                }
+                const double nv = (double)t.n_vert;
+                ctl->nudge_mean[0] = ax / nv / nv;
+                ctl->nudge_mean[1] = ay / nv / nv;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------- vertex
+struct VertexArgs {
+    LoopCtl *ctl;
+    const double *epart_cell;
+    int n_epart_cell;
+    double *epart_vert;
+    double *E_out;
+    double *maxf_out;
+    double eta;
+    int cur;
+    int nudge;  // 0 none, 1 v2v, 2 linear
+    double beta;
+    const void *Xt;
+    const void *g_lin;
+};
+
+__device__ __forceinline__ void relax_control(LoopCtl *ctl, double mf, int cur) {
+    ctl->iter += 1;
+    ctl->last_maxf = mf;
+    if (!(mf <= 1.7976931348623157e308)) {  // NaN or infinity
+        ctl->done = 1;
+        ctl->status = VTX_E_NONFINITE;
+        ctl->result_buf = cur;
+        return;
+    }
+    if (mf < ctl->tol) ctl->count += 1;
+    else ctl->count = 0;
+    if (ctl->count >= ctl->patience) {
+        ctl->done = 1;
+        ctl->status = VTX_CONVERGED;
+        ctl->result_buf = cur;
+    } else if (ctl->iter >= ctl->max_iter) {
+        ctl->done = 1;
+        ctl->status = VTX_NOT_CONVERGED;
+        ctl->result_buf = cur ^ 1;
+    }
+}
+
+template <typename PosT, typename M, int MODE>  // MODE 0: evaluate, 1: relaxation step
+__global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__restrict__ X,
+                                                   PosT *__restrict__ out, DevParams<PosT> p,
+                                                   const M *__restrict__ cap, VertexArgs a) {
+    if (MODE == 1 && a.ctl->done) return;
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    double el = 0.0, mf = 0.0;
+    if (v < t.n_vert) {
+        Star<PosT, M> s;
+        PosT xi, yi;
+        load_star<PosT, M>(t, X, p, cap, v, s, xi, yi);
+        M fx, fy;
+        star_force<PosT, M>(s, fx, fy);
+        if (MODE == 0) {
+            if (a.E_out)
+                el = 0.5 * ((double)s.lam[0] * (double)s.l[0] + (double)s.lam[1] * (double)s.l[1] +
+                            (double)s.lam[2] * (double)s.l[2]);
+            if (out) st2(out, v, (PosT)fx, (PosT)fy);
+            mf = fmax(fabs((double)fx), fabs((double)fy));
+            if (!(fx == fx) || !(fy == fy)) mf = INFINITY;
+        } else {
+            double gx = fx, gy = fy;
+            if (a.nudge == 1) {
+                const PosT *Xt = (const PosT *)a.Xt;
+                const double inv = 1.0 / (double)t.n_vert;
+                const double cx = min_image((double)xi - (double)Xt[2 * (int64_t)v], t.Lx) * inv;
+                const double cy = min_image((double)yi - (double)Xt[2 * (int64_t)v + 1], t.Ly) * inv;
+                gx -= a.beta * (cx - a.ctl->nudge_mean[0]);
+                gy -= a.beta * (cy - a.ctl->nudge_mean[1]);
+            } else if (a.nudge == 2) {
+                const double *g = (const double *)a.g_lin;
+                gx -= a.beta * (g[2 * (int64_t)v] - a.ctl->nudge_mean[0]);
+                gy -= a.beta * (g[2 * (int64_t)v + 1] - a.ctl->nudge_mean[1]);
+            }
+            mf = fmax(fabs(gx), fabs(gy));
+            if (!(gx == gx) || !(gy == gy)) mf = INFINITY;
+            st2(out, v, (PosT)((double)xi + a.eta * gx), (PosT)((double)yi + a.eta * gy));
+        }
+    }
+    if (MODE == 0 && a.E_out) {
+        const double s = block_sum(el, sh);
+        if (threadIdx.x == 0) a.epart_vert[blockIdx.x] = s;
+    }
+    if (MODE == 1 || a.maxf_out || a.E_out) {
+        const double m = block_max(mf, sh);
+        if (threadIdx.x == 0) {
+            atomicMax(&a.ctl->maxf_bits, (unsigned long long)__double_as_longlong(m));
+            if (last_block(&a.ctl->arrive)) {
+                const double mfin = __longlong_as_double(
+                    (long long)__hip_atomic_load(&a.ctl->maxf_bits, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT));
+                a.ctl->maxf_bits = 0ull;
+                if (MODE == 1) {
+                    relax_control(a.ctl, mfin, a.cur);
+                } else {
+                    if (a.maxf_out) *a.maxf_out = mfin;
+                    if (a.E_out) {
+                        double E = 0.0;
+                        for (int b = 0; b < a.n_epart_cell; ++b) E += ld_acquire(a.epart_cell + b);
+                        for (unsigned b = 0; b < gridDim.x; ++b) E += ld_acquire(a.epart_vert + b);
+                        *a.E_out = E;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- T1
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<PosT> p, M *cap,
+                                               LoopCtl *ctl, int32_t *list_g, double l_min,
+                                               double l_new) {
+    __shared__ int32_t buf[kT1SortCap];
+    __shared__ int32_t extra[kT1Extra];
+    __shared__ int32_t scan[kBlock];
+    __shared__ int s_changed;
+    if (ctl->done) return;
+    const int n = (int)ctl->t1_count;
+    if (n == 0) return;
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    int32_t *arr = np2 <= kT1SortCap ? buf : list_g;
+    // corner index -> edge id (each thread reads and writes only its own
+    // slots, so converting in place when arr == list_g is safe)
+    for (int i = threadIdx.x; i < np2; i += blockDim.x)
+        arr[i] = i < n ? t.he_edge[t.corner_he[list_g[i]]] : INT_MAX;
+    __syncthreads();
+    block_bitonic(arr, np2);
+    if (threadIdx.x == 0) {
+        T1Counts r = t1_sequential<PosT, M>(t, X, p, cap, arr, n, extra, l_min, l_new);
+        ctl->n_t1 += r.swaps;
+        ctl->n_stretch += r.stretches;
+        if (r.overflow) ctl->t1_overflow = 1;
+        ctl->t1_count = 0;
+        s_changed = r.changed;
+        if (r.changed) ctl->topo_changed = 1;
+    }
+    __syncthreads();
+    if (s_changed) {
+        const int bad = rebuild_rows_block(t, scan);
+        if (threadIdx.x == 0 && bad) ctl->t1_overflow = 2;
+    }
+}
+
+// -------------------------------------------------------------------- HVP
+// Directional derivatives of each cell's area and perimeter along v:
+//   dA = sum_k grad_k A . v_k,  grad_k A = 1/2 R(r_{k+1} - r_{k-1});
+//   dP = sum_k u_k . (v_{k+1} - v_k).
+// Stored as (2 K_A dA, 2 K_P dP).
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__restrict__ X,
+                                                     DevParams<PosT> p,
+                                                     const double *__restrict__ v,
+                                                     M *__restrict__ aux, LoopCtl *ctl) {
+    if (ctl && ctl->done) return;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= t.n_cell) return;
+    const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
+    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    const int32_t w0 = t.corner[rb];
+    const int v0 = id_of(w0);
+    const auto p0 = ld2(X, v0);
+    auto rel = [&](int k, M &rx, M &ry, M &vx, M &vy) {
+        const int32_t w = t.corner[rb + k];
+        const int vv = id_of(w);
+        if (k == 0) {
+            rx = 0;
+            ry = 0;
+        } else {
+            const auto q = ld2(X, vv);
+            rx = (M)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
+            ry = (M)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
+        }
+        const auto vq = ld2(v, vv);
+        vx = (M)vq.x;
+        vy = (M)vq.y;
+    };
+    M rpx, rpy, vdum0, vdum1;
+    rel(n - 1, rpx, rpy, vdum0, vdum1);
+    M rcx, rcy, vcx, vcy;
+    rel(0, rcx, rcy, vcx, vcy);
+    M dA = 0, dP = 0;
+    for (int k = 0; k < n; ++k) {
+        const int kn = (k + 1 == n) ? 0 : k + 1;
+        M rnx, rny, vnx, vny;
+        rel(kn, rnx, rny, vnx, vny);
+        const M gx = (M)0.5 * (rny - rpy), gy = (M)-0.5 * (rnx - rpx);
+        dA += gx * vcx + gy * vcy;
+        const M dx = rnx - rcx, dy = rny - rcy;
+        const M l = sqrt(dx * dx + dy * dy);
+        if (l > (M)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
+        rpx = rcx;
+        rpy = rcy;
+        rcx = rnx;
+        rcy = rny;
+        vcx = vnx;
+        vcy = vny;
+    }
+    st2(aux, c, (M)2 * (M)p.ka(c) * dA, (M)2 * (M)p.kp(c) * dP);
+}
+
+// (H v)_i = sum_k [ T_k w_k - u_k (B_k + B_{k-1}) + 1/2 R(d_k)(G_k - G_{k-1})
+//                   + 1/2 R(v_{j_k} - v_i)(cA_k - cA_{k-1}) ]
+// with w_k = (I - u_k u_k^T)(v_i - v_{j_k}) / l_k, T_k the edge tension,
+// G = 2K_A dA and B = 2K_P dP of the sector cells.  Also accumulates the
+// FP64 dot v . Hv and, in CG, alpha = rr / (p . Ap).
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *__restrict__ X,
+                                                       DevParams<PosT> p,
+                                                       const M *__restrict__ cap,
+                                                       const M *__restrict__ aux,
+                                                       const double *__restrict__ v,
+                                                       double *__restrict__ Hv,
+                                                       double *__restrict__ dpart,
+                                                       LoopCtl *ctl) {
+    if (ctl && ctl->done) return;
+    __shared__ double sh[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double dot = 0.0;
+    if (i < t.n_vert) {
+        Star<PosT, M> s;
+        PosT xi, yi;
+        load_star<PosT, M>(t, X, p, cap, i, s, xi, yi);
+        const auto vi = ld2(v, i);
+        M G[3], B[3], vx[3], vy[3];
+        const int nv = t.n_vert;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const auto g = ld2(aux, t.star_cell[k * nv + i]);
+            G[k] = g.x;
+            B[k] = g.y;
+            const auto vj = ld2(v, s.nb[k]);
+            vx[k] = (M)(vj.x - vi.x);  // v_{j_k} - v_i
+            vy[k] = (M)(vj.y - vi.y);
+        }
+        M hx = 0, hy = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int km = (k + 2) % 3;
+            const M T = s.lam[k] + s.cP[k] + s.cP[km];
+            const M du = -(vx[k] * s.ux[k] + vy[k] * s.uy[k]);  // (v_i - v_j) . u
+            const M wx = (-vx[k] - du * s.ux[k]) * s.inv[k];
+            const M wy = (-vy[k] - du * s.uy[k]) * s.inv[k];
+            const M Bs = B[k] + B[km];
+            const M dG = (M)0.5 * (G[k] - G[km]);
+            const M dC = (M)0.5 * (s.cA[k] - s.cA[km]);
+            hx += T * wx - s.ux[k] * Bs + dG * s.dy[k] + dC * vy[k];
+            hy += T * wy - s.uy[k] * Bs - dG * s.dx[k] - dC * vx[k];
+        }
+        st2(Hv, i, (double)hx, (double)hy);
+        dot = vi.x * (double)hx + vi.y * (double)hy;
+    }
+    if (dpart) {
+        const double bs = block_sum(dot, sh);
+        if (threadIdx.x == 0) {
+            dpart[blockIdx.x] = bs;
+            if (ctl && last_block(&ctl->arrive)) {
+                double pAp = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) pAp += ld_acquire(dpart + b);
+                ctl->pAp = pAp;
+                if (!(pAp > 0.0)) {
+                    ctl->done = 1;
+                    ctl->status = VTX_CG_NEG_CURVATURE;
+                } else {
+                    ctl->alpha = ctl->rr / pAp;
+                }
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------- CG
+// Sum over vertices of a 2-vector field -> ctl->nudge_mean (as a mean).
+__global__ __launch_bounds__(kBlock) void k_mean2(const double *__restrict__ a, int nv,
+                                                  double *__restrict__ part, LoopCtl *ctl,
+                                                  double *mean_out) {
+    __shared__ double sh[kBlock / 64];
+    double sx = 0.0, sy = 0.0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < nv; v += gridDim.x * kBlock) {
+        sx += a[2 * (int64_t)v];
+        sy += a[2 * (int64_t)v + 1];
+    }
+    const double bx = block_sum(sx, sh);
+    const double by = block_sum(sy, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = bx;
+        part[2 * blockIdx.x + 1] = by;
+        if (last_block(&ctl->arrive2)) {
+            double ax = 0.0, ay = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                ax += ld_acquire(part + 2 * b);
+                ay += ld_acquire(part + 2 * b + 1);
+            }
+            mean_out[0] = ax / (double)nv;
+            mean_out[1] = ay / (double)nv;
+        }
+    }
+}
+
+// v <- v - mean  (in place); also usable to produce r = b - mean.
+__global__ __launch_bounds__(kBlock) void k_sub_mean(const double *__restrict__ a,
+                                                     double *__restrict__ out, int nv,
+                                                     const double *mean) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    out[2 * (int64_t)v] = a[2 * (int64_t)v] - mean[0];
+    out[2 * (int64_t)v + 1] = a[2 * (int64_t)v + 1] - mean[1];
+}
+
+// r = b - mean(b), p = r, x = 0, rr = r . r
+__global__ __launch_bounds__(kBlock) void k_cg_init(const double *__restrict__ b, int nv,
+                                                    const double *mean, double *__restrict__ x,
+                                                    double *__restrict__ r,
+                                                    double *__restrict__ q,
+                                                    double *__restrict__ part, LoopCtl *ctl) {
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    double rr = 0.0;
+    if (v < nv) {
+        const double rx = b[2 * (int64_t)v] - mean[0], ry = b[2 * (int64_t)v + 1] - mean[1];
+        r[2 * (int64_t)v] = rx;
+        r[2 * (int64_t)v + 1] = ry;
+        q[2 * (int64_t)v] = rx;
+        q[2 * (int64_t)v + 1] = ry;
+        x[2 * (int64_t)v] = 0.0;
+        x[2 * (int64_t)v + 1] = 0.0;
+        rr = rx * rx + ry * ry;
+    }
+    const double bs = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        if (last_block(&ctl->arrive)) {
+            double s = 0.0;
+            for (unsigned k = 0; k < gridDim.x; ++k) s += ld_acquire(part + k);
+            ctl->rr = s;
+            ctl->rr0 = s;
+            ctl->rel_res = s > 0.0 ? 1.0 : 0.0;
+            if (!(s > 0.0)) {
+                ctl->done = 1;
+                ctl->status = VTX_CONVERGED;
+            }
+        }
+    }
+}
+
+// x += alpha q, r -= alpha Aq, then beta = r.r / rr and the stopping tests.
+__global__ __launch_bounds__(kBlock) void k_cg_update(double *__restrict__ x,
+                                                      double *__restrict__ r,
+                                                      const double *__restrict__ q,
+                                                      const double *__restrict__ Aq, int nv,
+                                                      double *__restrict__ part, LoopCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    const double al = ctl->alpha;
+    double rr = 0.0;
+    if (v < nv) {
+        const int64_t k = 2 * (int64_t)v;
+        x[k] += al * q[k];
+        x[k + 1] += al * q[k + 1];
+        const double r0 = r[k] - al * Aq[k], r1 = r[k + 1] - al * Aq[k + 1];
+        r[k] = r0;
+        r[k + 1] = r1;
+        rr = r0 * r0 + r1 * r1;
+    }
+    const double bs = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        if (last_block(&ctl->arrive)) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
+            ctl->beta_cg = s / ctl->rr;
+            ctl->rr = s;
+            ctl->cg_iter += 1;
+            ctl->rel_res = sqrt(s / ctl->rr0);
+            if (sqrt(s) <= ctl->tol * sqrt(ctl->rr0)) {
+                ctl->done = 1;
+                ctl->status = VTX_CONVERGED;
+            } else if (ctl->cg_iter >= ctl->max_iter) {
+                ctl->done = 1;
+                ctl->status = VTX_CG_MAXITER;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_dir(const double *__restrict__ r,
+                                                   double *__restrict__ q, int nv,
+                                                   LoopCtl *ctl) {
+    if (ctl->done) return;
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const double be = ctl->beta_cg;
+    const int64_t k = 2 * (int64_t)v;
+    q[k] = r[k] + be * q[k];
+    q[k + 1] = r[k + 1] + be * q[k + 1];
+}
+
+// ------------------------------------------------------------ contractions
+// theta = lambda:  g_e = -(d2E/dX dlambda_e) . mu = -u_e . (mu_tgt - mu_src)
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_contract_lambda(DevTissue t, const PosT *X,
+                                                            const double *mu, double *g) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= t.n_edge) return;
+    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
+    const int s = r[HS], q = r[HG];
+    const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+    const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+    const double l = sqrt(dx * dx + dy * dy);
+    g[e] = l > 0.0 ? -(dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
+                       dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l
+                   : 0.0;
+}
+
+// theta = P0:  g_c = -(d2E/dX dP0_c) . mu = 2 K_P grad P_c . mu
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_contract_p0(DevTissue t, const PosT *X,
+                                                        DevParams<PosT> p, const double *mu,
+                                                        double *g) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= t.n_cell) return;
+    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    double dP = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int h = t.corner_he[rb + k];
+        const int32_t *r = t.he + 8 * (int64_t)h;
+        const int s = r[HS], q = r[HG];
+        const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+        const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+        const double l = sqrt(dx * dx + dy * dy);
+        if (l > 0.0)
+            dP += (dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
+                   dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l;
+    }
+    g[c] = 2.0 * (double)p.kp(c) * dP;
+}
+
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_edge_len(DevTissue t, const PosT *X, double *len) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= t.n_edge) return;
+    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
+    const int s = r[HS], q = r[HG];
+    const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+    const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+    len[e] = sqrt(dx * dx + dy * dy);
+}
+
+// Exact (double) area and perimeter of every cell, walking the table.
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_cell_exact(DevTissue t, const PosT *X, double *A,
+                                                       double *P) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= t.n_cell) return;
+    PosOverride<PosT> none{-1, -1, 0, 0, 0, 0};
+    double a, per;
+    cell_walk<PosT>(t, X, t.cell_he[c], none, a, per);
+    if (A) A[c] = a;
+    if (P) P[c] = per;
+}
+
+// EP estimates from the two nudged states.
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_ep_lambda(DevTissue t, const PosT *Xp,
+                                                      const PosT *Xm, double beta, double *g) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= t.n_edge) return;
+    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
+    const int s = r[HS], q = r[HG];
+    double l[2];
+    const PosT *Xs[2] = {Xp, Xm};
+    for (int a = 0; a < 2; ++a) {
+        const PosT *X = Xs[a];
+        const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+        const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+        l[a] = sqrt(dx * dx + dy * dy);
+    }
+    g[e] = (l[0] - l[1]) / beta;
+}
+
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_ep_p0(DevTissue t, const PosT *Xp, const PosT *Xm,
+                                                  DevParams<PosT> p, double beta, double *g) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= t.n_cell) return;
+    PosOverride<PosT> none{-1, -1, 0, 0, 0, 0};
+    double a, pp, pm;
+    cell_walk<PosT>(t, Xp, t.cell_he[c], none, a, pp);
+    cell_walk<PosT>(t, Xm, t.cell_he[c], none, a, pm);
+    g[c] = -2.0 * (double)p.kp(c) * (pp - pm) / beta;
+}
+
+// v2v cost and gradient (minimum image).
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_v2v(DevTissue t, const PosT *X, const PosT *Xt,
+                                                double *grad, double *part, LoopCtl *ctl,
+                                                double *C_out) {
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    double c = 0.0;
+    if (v < t.n_vert) {
+        const double dx = min_image((double)X[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
+        const double dy = min_image((double)X[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
+        c = dx * dx + dy * dy;
+        if (grad) {
+            grad[2 * (int64_t)v] = dx / (double)t.n_vert;
+            grad[2 * (int64_t)v + 1] = dy / (double)t.n_vert;
+        }
+    }
+    if (C_out) {
+        const double bs = block_sum(c, sh);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = bs;
+            if (last_block(&ctl->arrive)) {
+                double s = 0.0;
+                for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
+                *C_out = s / (2.0 * (double)t.n_vert);
+            }
+        }
+    }
+}
+
+// g . X (linear nudge energy)
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_dot_pos(const PosT *g, const PosT *X, int nv,
+                                                    double *part, LoopCtl *ctl, double *out) {
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    double c = 0.0;
+    if (v < nv)
+        c = (double)g[2 * (int64_t)v] * (double)X[2 * (int64_t)v] +
+            (double)g[2 * (int64_t)v + 1] * (double)X[2 * (int64_t)v + 1];
+    const double bs = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        if (last_block(&ctl->arrive)) {
+            double s = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
+            *out = s;
+        }
+    }
+}
+
+// mean of a position-typed 2-vector field (linear nudge) into mean_out
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_mean_pos(const PosT *a, int nv, double *part,
+                                                     LoopCtl *ctl, double *mean_out) {
+    __shared__ double sh[kBlock / 64];
+    double sx = 0.0, sy = 0.0;
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < nv; v += gridDim.x * kBlock) {
+        sx += (double)a[2 * (int64_t)v];
+        sy += (double)a[2 * (int64_t)v + 1];
+    }
+    const double bx = block_sum(sx, sh);
+    const double by = block_sum(sy, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = bx;
+        part[2 * blockIdx.x + 1] = by;
+        if (last_block(&ctl->arrive2)) {
+            double ax = 0.0, ay = 0.0;
+            for (unsigned b = 0; b < gridDim.x; ++b) {
+                ax += ld_acquire(part + 2 * b);
+                ay += ld_acquire(part + 2 * b + 1);
+            }
+            mean_out[0] = ax / (double)nv;
+            mean_out[1] = ay / (double)nv;
+        }
+    }
+}
+
+// ================================================================ launchers
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename PosT>
+static DevParams<PosT> dev_params(const ParamsRaw &r) {
+    DevParams<PosT> p;
+    p.KA = (const PosT *)r.KA;
+    p.A0 = (const PosT *)r.A0;
+    p.KP = (const PosT *)r.KP;
+    p.P0 = (const PosT *)r.P0;
+    p.lam = (const PosT *)r.lam;
+    p.KA_s = (PosT)r.KA_s;
+    p.A0_s = (PosT)r.A0_s;
+    p.KP_s = (PosT)r.KP_s;
+    p.P0_s = (PosT)r.P0_s;
+    p.lam_s = (PosT)r.lam_s;
+    return p;
+}
+
+template <typename PosT, typename M>
+static void eval_impl(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                      double *E, void *F, double *maxf, hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    LoopCtl *ectl = w.ctl + 1;
+    const unsigned gc = blocks_for(t.n_cell), gv = blocks_for(t.n_vert);
+    hipLaunchKernelGGL((k_cell<PosT, M>), dim3(gc), dim3(kBlock), 0, s, t, (const PosT *)X, p,
+                       (M *)w.cap, w.partials, ectl, (int32_t *)nullptr, (M)0,
+                       E ? (int)F_ENERGY : 0, (const PosT *)nullptr, (double *)nullptr);
+    VertexArgs a{};
+    a.ctl = ectl;
+    a.epart_cell = w.partials;
+    a.n_epart_cell = (int)gc;
+    a.epart_vert = w.partials2;
+    a.E_out = E;
+    a.maxf_out = maxf;
+    hipLaunchKernelGGL((k_vertex<PosT, M, 0>), dim3(gv), dim3(kBlock), 0, s, t, (const PosT *)X,
+                       (PosT *)F, p, (const M *)w.cap, a);
+}
+
+void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                 const ParamsRaw &p, double *E, void *F, double *maxf, hipStream_t s) {
+    if (mode == VTX_F32) eval_impl<float, float>(t, w, X, p, E, F, maxf, s);
+    else if (mode == VTX_F64) eval_impl<double, double>(t, w, X, p, E, F, maxf, s);
+    else eval_impl<double, float>(t, w, X, p, E, F, maxf, s);
+}
+
+template <typename PosT, typename M>
+static void relax_iter_impl(const DevTissue &t, const Workspace &w, void *Xc, void *Xn, int cur,
+                            const ParamsRaw &pr, const RelaxArgs &ra, hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    LoopCtl *ctl = w.ctl;
+    const unsigned gc = blocks_for(t.n_cell), gv = blocks_for(t.n_vert);
+    int flags = 0;
+    if (ra.t1_enable) flags |= F_T1DET;
+    if (ra.nudge == 1) flags |= F_NUDGE_V2V;
+    // detection threshold slightly above l_min: the exact FP64 test is in k_t1
+    const M lmin2 = (M)(ra.l_min * ra.l_min * (1.0 + 1e-4));
+    hipLaunchKernelGGL((k_cell<PosT, M>), dim3(gc), dim3(kBlock), 0, s, t, (const PosT *)Xc, p,
+                       (M *)w.cap, (double *)nullptr, ctl, w.t1_list, lmin2, flags,
+                       (const PosT *)ra.X_target, w.partials);
+    if (ra.t1_enable)
+        hipLaunchKernelGGL((k_t1<PosT, M>), dim3(1), dim3(kBlock), 0, s, t, (PosT *)Xc, p,
+                           (M *)w.cap, ctl, w.t1_list, ra.l_min, ra.l_new);
+    VertexArgs a{};
+    a.ctl = ctl;
+    a.eta = ra.eta;
+    a.cur = cur;
+    a.nudge = ra.nudge;
+    a.beta = ra.beta;
+    a.Xt = ra.X_target;
+    a.g_lin = ra.g_lin;
+    hipLaunchKernelGGL((k_vertex<PosT, M, 1>), dim3(gv), dim3(kBlock), 0, s, t,
+                       (const PosT *)Xc, (PosT *)Xn, p, (const M *)w.cap, a);
+}
+
+void launch_relax_iter(const DevTissue &t, const Workspace &w, int mode, void *Xc, void *Xn,
+                       int cur, const ParamsRaw &p, const RelaxArgs &ra, hipStream_t s) {
+    if (mode == VTX_F32) relax_iter_impl<float, float>(t, w, Xc, Xn, cur, p, ra, s);
+    else if (mode == VTX_F64) relax_iter_impl<double, double>(t, w, Xc, Xn, cur, p, ra, s);
+    else relax_iter_impl<double, float>(t, w, Xc, Xn, cur, p, ra, s);
+}
+
+template <typename PosT, typename M>
+static void t1_impl(const DevTissue &t, const Workspace &w, void *X, const ParamsRaw &pr,
+                    double l_min, double l_new, hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    LoopCtl *ectl = w.ctl + 1;
+    const unsigned gc = blocks_for(t.n_cell);
+    const M lmin2 = (M)(l_min * l_min * (1.0 + 1e-4));
+    hipLaunchKernelGGL((k_cell<PosT, M>), dim3(gc), dim3(kBlock), 0, s, t, (const PosT *)X, p,
+                       (M *)w.cap, (double *)nullptr, ectl, w.t1_list, lmin2, (int)F_T1DET,
+                       (const PosT *)nullptr, (double *)nullptr);
+    hipLaunchKernelGGL((k_t1<PosT, M>), dim3(1), dim3(kBlock), 0, s, t, (PosT *)X, p,
+                       (M *)w.cap, ectl, w.t1_list, l_min, l_new);
+}
+
+void launch_t1(const DevTissue &t, const Workspace &w, int mode, void *X, const ParamsRaw &p,
+               double l_min, double l_new, hipStream_t s) {
+    if (mode == VTX_F32) t1_impl<float, float>(t, w, X, p, l_min, l_new, s);
+    else if (mode == VTX_F64) t1_impl<double, double>(t, w, X, p, l_min, l_new, s);
+    else t1_impl<double, float>(t, w, X, p, l_min, l_new, s);
+}
+
+template <typename PosT, typename M>
+static void cap_impl(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                     hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    hipLaunchKernelGGL((k_cell<PosT, M>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t,
+                       (const PosT *)X, p, (M *)w.cap, (double *)nullptr, w.ctl + 1,
+                       (int32_t *)nullptr, (M)0, 0, (const PosT *)nullptr, (double *)nullptr);
+}
+
+void launch_cell_coeffs(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                        const ParamsRaw &p, hipStream_t s) {
+    if (mode == VTX_F32) cap_impl<float, float>(t, w, X, p, s);
+    else if (mode == VTX_F64) cap_impl<double, double>(t, w, X, p, s);
+    else cap_impl<double, float>(t, w, X, p, s);
+}
+
+template <typename PosT, typename M>
+static void hvp_impl(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                     const double *v, double *Hv, double *dpart, LoopCtl *ctl, hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    hipLaunchKernelGGL((k_hvp_cell<PosT, M>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t,
+                       (const PosT *)X, p, v, (M *)w.cell_aux, ctl);
+    hipLaunchKernelGGL((k_hvp_vertex<PosT, M>), dim3(blocks_for(t.n_vert)), dim3(kBlock), 0, s,
+                       t, (const PosT *)X, p, (const M *)w.cap, (const M *)w.cell_aux, v, Hv,
+                       dpart, ctl);
+}
+
+void launch_hvp(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                const ParamsRaw &p, const double *v, double *Hv, double *dpart, LoopCtl *ctl,
+                hipStream_t s) {
+    if (mode == VTX_F32) hvp_impl<float, float>(t, w, X, p, v, Hv, dpart, ctl, s);
+    else if (mode == VTX_F64) hvp_impl<double, double>(t, w, X, p, v, Hv, dpart, ctl, s);
+    else hvp_impl<double, float>(t, w, X, p, v, Hv, dpart, ctl, s);
+}
+
+void launch_cg_init(const Workspace &w, int nv, const double *b, hipStream_t s) {
+    double *x = w.cg, *r = w.cg + 2 * (int64_t)nv, *q = w.cg + 4 * (int64_t)nv;
+    const unsigned gv = blocks_for(nv);
+    const unsigned gm = gv < 1024 ? gv : 1024;
+    hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, b, nv, w.partials2, w.ctl,
+                       w.scal);
+    hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, b, nv, (const double *)w.scal,
+                       x, r, q, w.partials, w.ctl);
+}
+
+void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                    const ParamsRaw &p, hipStream_t s) {
+    const int nv = t.n_vert;
+    double *x = w.cg, *r = w.cg + 2 * (int64_t)nv, *q = w.cg + 4 * (int64_t)nv,
+           *Aq = w.cg + 6 * (int64_t)nv;
+    launch_hvp(t, w, mode, X, p, q, Aq, w.partials, w.ctl, s);
+    const unsigned gv = blocks_for(nv);
+    hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, x, r, (const double *)q,
+                       (const double *)Aq, nv, w.partials, w.ctl);
+    hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(kBlock), 0, s, (const double *)r, q, nv, w.ctl);
+}
+
+void launch_project(const Workspace &w, int nv, double *x, hipStream_t s) {
+    const unsigned gv = blocks_for(nv);
+    const unsigned gm = gv < 1024 ? gv : 1024;
+    hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, (const double *)x, nv, w.partials2,
+                       w.ctl + 1, w.scal + 2);
+    hipLaunchKernelGGL(k_sub_mean, dim3(gv), dim3(kBlock), 0, s, (const double *)x, x, nv,
+                       (const double *)(w.scal + 2));
+}
+
+template <typename PosT>
+static void contract_impl(const DevTissue &t, const void *X, const ParamsRaw &pr, int theta,
+                          const double *mu, double *g, hipStream_t s) {
+    if (theta == VTX_THETA_LAMBDA)
+        hipLaunchKernelGGL((k_contract_lambda<PosT>), dim3(blocks_for(t.n_edge)), dim3(kBlock), 0,
+                           s, t, (const PosT *)X, mu, g);
+    else
+        hipLaunchKernelGGL((k_contract_p0<PosT>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s,
+                           t, (const PosT *)X, dev_params<PosT>(pr), mu, g);
+}
+
+void launch_contract(const DevTissue &t, int mode, const void *X, const ParamsRaw &p, int theta,
+                     const double *mu, double *g, hipStream_t s) {
+    if (mode == VTX_F32) contract_impl<float>(t, X, p, theta, mu, g, s);
+    else contract_impl<double>(t, X, p, theta, mu, g, s);
+}
+
+template <typename PosT>
+static void ep_impl(const DevTissue &t, const void *Xp, const void *Xm, const ParamsRaw &pr,
+                    int theta, double beta, double *g, hipStream_t s) {
+    if (theta == VTX_THETA_LAMBDA)
+        hipLaunchKernelGGL((k_ep_lambda<PosT>), dim3(blocks_for(t.n_edge)), dim3(kBlock), 0, s, t,
+                           (const PosT *)Xp, (const PosT *)Xm, beta, g);
+    else
+        hipLaunchKernelGGL((k_ep_p0<PosT>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t,
+                           (const PosT *)Xp, (const PosT *)Xm, dev_params<PosT>(pr), beta, g);
+}
+
+void launch_ep(const DevTissue &t, int mode, const void *Xp, const void *Xm, const ParamsRaw &p,
+               int theta, double beta, double *g, hipStream_t s) {
+    if (mode == VTX_F32) ep_impl<float>(t, Xp, Xm, p, theta, beta, g, s);
+    else ep_impl<double>(t, Xp, Xm, p, theta, beta, g, s);
+}
+
+void launch_edge_len(const DevTissue &t, int mode, const void *X, double *len, hipStream_t s) {
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_edge_len<float>), dim3(blocks_for(t.n_edge)), dim3(kBlock), 0, s, t,
+                           (const float *)X, len);
+    else
+        hipLaunchKernelGGL((k_edge_len<double>), dim3(blocks_for(t.n_edge)), dim3(kBlock), 0, s, t,
+                           (const double *)X, len);
+}
+
+void launch_cell_exact(const DevTissue &t, int mode, const void *X, double *A, double *P,
+                       hipStream_t s) {
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_cell_exact<float>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s,
+                           t, (const float *)X, A, P);
+    else
+        hipLaunchKernelGGL((k_cell_exact<double>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s,
+                           t, (const double *)X, A, P);
+}
+
+void launch_v2v(const DevTissue &t, const Workspace &w, int mode, const void *X, const void *Xt,
+                double *C, double *grad, hipStream_t s) {
+    const unsigned gv = blocks_for(t.n_vert);
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_v2v<float>), dim3(gv), dim3(kBlock), 0, s, t, (const float *)X,
+                           (const float *)Xt, grad, w.partials2, w.ctl + 1, C);
+    else
+        hipLaunchKernelGGL((k_v2v<double>), dim3(gv), dim3(kBlock), 0, s, t, (const double *)X,
+                           (const double *)Xt, grad, w.partials2, w.ctl + 1, C);
+}
+
+void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const void *X,
+                    double *out, hipStream_t s) {
+    const unsigned gv = blocks_for(nv);
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_dot_pos<float>), dim3(gv), dim3(kBlock), 0, s, (const float *)g,
+                           (const float *)X, nv, w.partials2, w.ctl + 1, out);
+    else
+        hipLaunchKernelGGL((k_dot_pos<double>), dim3(gv), dim3(kBlock), 0, s, (const double *)g,
+                           (const double *)X, nv, w.partials2, w.ctl + 1, out);
+}
+
+void launch_mean_pos(const Workspace &w, int mode, int nv, const void *a, double *mean_out,
+                     hipStream_t s) {
+    const unsigned gv = blocks_for(nv);
+    const unsigned gm = gv < 1024 ? gv : 1024;
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_mean_pos<float>), dim3(gm), dim3(kBlock), 0, s, (const float *)a, nv,
+                           w.partials2, w.ctl + 1, mean_out);
+    else
+        hipLaunchKernelGGL((k_mean_pos<double>), dim3(gm), dim3(kBlock), 0, s, (const double *)a,
+                           nv, w.partials2, w.ctl + 1, mean_out);
+}
+
+}  // namespace vtx

@@ -1,0 +1,287 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Tolerances: forces within 1e-5 of max |F| (relative, the requirement for the
+FP32 path; the FP64 path is held to 1e-10), energies within the rounding of
+each precision, topology after T1 bit-exact, relaxed positions within 1e-4
+of the mean edge length."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_06896_amd import tissue_gen as g
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vtx():
+    from paper_2604_06896_amd import vtx as V
+    V.lib()
+    assert torch.cuda.is_available()
+    return V
+
+
+def _rand_params(t, rng):
+    p = g.uniform_params(t)
+    p.KA = rng.uniform(0.5, 1.5, t.n_cell)
+    p.A0 = rng.uniform(0.8, 1.2, t.n_cell)
+    p.KP = rng.uniform(0.5, 1.5, t.n_cell)
+    p.P0 = rng.uniform(3.5, 4.0, t.n_cell)
+    p.lam = rng.uniform(0.0, 0.2, t.n_edge)
+    return p
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _force_err(F, Fo):
+    return np.abs(F - Fo).max() / np.abs(Fo).max()
+
+
+# ----------------------------------------------------------- energy / forces
+
+@pytest.mark.parametrize("n_cell,seed", [(100, 101), (1000, 5), (37, 9)])
+def test_energy_forces_f64(vtx, oracle, n_cell, seed):
+    rng = np.random.default_rng(seed)
+    t = g.random_tissue(n_cell, np.sqrt(n_cell), rng=rng)
+    p = _rand_params(t, rng)
+    X = t.X + rng.normal(0, 0.02, t.X.shape)
+    Eo, Fo = oracle.energy_forces(oracle.Mesh.from_tissue(t), X, p)
+    T = vtx.Tissue.from_tissue(t)
+    E, F, mf = T.energy_forces(_dev(X), vtx.Params.from_numpy(p), mode="f64", want_maxf=True)
+    F = F.cpu().numpy()
+    assert _force_err(F, Fo) < 1e-10
+    assert E.item() == pytest.approx(Eo, rel=1e-12)
+    assert mf.item() == pytest.approx(np.abs(Fo).max(), rel=1e-10)
+
+
+@pytest.mark.parametrize("mode", ["f32", "mixed"])
+def test_energy_forces_reduced_precision(vtx, oracle, mode):
+    t, p = g.workload_single_10k()
+    dt = torch.float32 if mode == "f32" else torch.float64
+    Xd = _dev(t.X, dt)
+    Xin = Xd.double().cpu().numpy()       # the oracle sees exactly the GPU's input
+    Eo, Fo = oracle.energy_forces(oracle.Mesh.from_tissue(t), Xin, p)
+    T = vtx.Tissue.from_tissue(t)
+    E, F, _ = T.energy_forces(Xd, vtx.Params.from_numpy(p, dtype=dt), mode=mode)
+    err = _force_err(F.double().cpu().numpy(), Fo)
+    print(f"{mode}: max |dF| / max |F| = {err:.3e}, E rel err = {abs(E.item() / Eo - 1):.3e}")
+    assert err < 1e-5
+    assert E.item() == pytest.approx(Eo, rel=1e-6)
+
+
+def test_forces_scalar_params_and_hex_lattice(vtx, oracle):
+    s = 0.62
+    t = g.hex_lattice(6, 8, s)
+    T = vtx.Tissue.from_tissue(t)
+    prm = vtx.Params(KA=1.3, A0=0.9, KP=0.7, P0=3.5, lam=0.2)
+    E, F, _ = T.energy_forces(_dev(t.X), prm, mode="f64")
+    Ah, Ph = 1.5 * np.sqrt(3.0) * s * s, 6 * s
+    N = t.n_cell
+    assert E.item() == pytest.approx(N * (1.3 * (Ah - 0.9) ** 2 + 0.7 * (Ph - 3.5) ** 2)
+                                     + 3 * N * 0.2 * s, rel=1e-12)
+    assert F.abs().max().item() < 1e-12
+
+
+def test_forces_deterministic(vtx):
+    t, p = g.workload_single_10k()
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X, torch.float32)
+    P = vtx.Params.from_numpy(p, dtype=torch.float32)
+    E1, F1, _ = T.energy_forces(Xd, P, mode="f32")
+    E2, F2, _ = T.energy_forces(Xd, P, mode="f32")
+    assert torch.equal(F1, F2) and E1.item() == E2.item()
+
+
+def test_force_kernel_full_size_1m_cells(vtx, oracle):
+    """The 10^6-cell workload in the launch configuration the benchmark times
+    (FP32 positions); all 4e6 force components against the oracle."""
+    t, p = g.workload_force_1m()
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X, torch.float32)
+    P = vtx.Params(KA=1.0, A0=1.0, KP=1.0, P0=3.75,
+                   lam=torch.as_tensor(p.lam, dtype=torch.float32, device="cuda"))
+    E, F, _ = T.energy_forces(Xd, P, mode="f32")
+    pin = g.uniform_params(t, P0=3.75)
+    pin.lam = torch.as_tensor(p.lam, dtype=torch.float32).double().numpy()
+    Eo, Fo = oracle.energy_forces(oracle.Mesh.from_tissue(t), Xd.double().cpu().numpy(), pin)
+    err = _force_err(F.double().cpu().numpy(), Fo)
+    print(f"1e6 cells f32: max |dF| / max |F| = {err:.3e}")
+    assert err < 1e-5
+    assert E.item() == pytest.approx(Eo, rel=1e-6)
+
+
+def test_geometry_and_lengths(vtx, oracle):
+    rng = np.random.default_rng(2)
+    t = g.random_tissue(200, np.sqrt(200.0), rng=rng)
+    T = vtx.Tissue.from_tissue(t)
+    A, P = T.cell_geometry(_dev(t.X))
+    Ao, Po, _ = oracle.cells(oracle.Mesh.from_tissue(t), t.X)
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-12)
+    np.testing.assert_allclose(P.cpu().numpy(), Po, rtol=1e-12)
+    L = T.edge_lengths(_dev(t.X))
+    np.testing.assert_allclose(L.cpu().numpy(), oracle.edge_lengths(oracle.Mesh.from_tissue(t), t.X),
+                               rtol=1e-12)
+
+
+# ----------------------------------------------------------------------- T1
+
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_t1_pass_bit_exact_topology(vtx, oracle, mode):
+    t, p = g.workload_single_10k(n_cell=2000, seed=211)
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    n_sw, n_st = oracle.t1_pass(m, X, p, 0.01, 0.02)
+    assert n_sw > 0 and n_st > 0
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    a, b = T.t1(Xd, vtx.Params.from_numpy(p), 0.01, 0.02, mode=mode)
+    assert (a, b) == (n_sw, n_st)
+    np.testing.assert_array_equal(T.topology(), m.he)
+    assert np.abs(Xd.cpu().numpy() - X).max() < 1e-12
+    # the staged layouts follow: forces after the pass match the oracle
+    _, F, _ = T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
+    _, Fo = oracle.energy_forces(m, X, p)
+    assert _force_err(F.cpu().numpy(), Fo) < 1e-10
+
+
+# ---------------------------------------------------------------- relaxation
+
+def test_relax_fixed_iterations_f64(vtx, oracle):
+    """100-cell tissue, P0 = 3.8, no line tension, no T1: 400 GD steps."""
+    t, p = g.workload_single_100()
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    ro = oracle.relax(m, X, p, eta=1e-2, tol=0.0, patience=1, max_iter=400)
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    r = T.relax(Xd, vtx.Params(P0=3.8, lam=0.0), mode="f64", eta=1e-2, tol=0.0, max_iter=400,
+                chunk=64)
+    assert r["iters"] == ro["iters"] == 400 and r["status"] == 1
+    assert np.abs(Xd.cpu().numpy() - X).max() < 1e-9
+    assert r["max_f"] == pytest.approx(ro["max_f"], rel=1e-6)
+    assert r["energy"] == pytest.approx(ro["energy"], rel=1e-10)
+
+
+def test_relax_with_t1_to_equilibrium_f64(vtx, oracle):
+    """100-cell tissue with T1 (l_min 0.01) relaxed to max |F| < 1e-6."""
+    t, p = g.workload_single_100()
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    ro = oracle.relax(m, X, p, eta=1e-2, tol=1e-6, patience=1, max_iter=200000,
+                      t1_enable=True, l_min=0.01)
+    assert ro["status"] == 0
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    r = T.relax(Xd, vtx.Params(P0=3.8, lam=0.0), mode="f64", eta=1e-2, tol=1e-6,
+                max_iter=200000, t1_enable=True, l_min=0.01)
+    print("gpu", r, "oracle", ro)
+    assert r["status"] == 0
+    assert (r["n_t1"], r["n_stretch"]) == (ro["n_t1"], ro["n_stretch"])
+    np.testing.assert_array_equal(T.topology(), m.he)
+    ell = oracle.edge_lengths(m, X).mean()
+    d = Xd.cpu().numpy() - X
+    d -= t.Lx * np.round(d / t.Lx)
+    assert np.abs(d).max() < 1e-4 * ell
+    # the oracle confirms the returned state is an equilibrium
+    _, Fo = oracle.energy_forces(m, Xd.cpu().numpy(), p)
+    assert np.abs(Fo).max() < 1e-6
+
+
+def test_relax_mixed_precision_reaches_tolerance(vtx, oracle):
+    """10^3-cell tissue, FP32 force arithmetic on FP64 positions, T1 on."""
+    t, p = g.workload_single_10k(n_cell=1000, seed=221)
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    r = T.relax(Xd, vtx.Params.from_numpy(p), mode="mixed", eta=3e-3, tol=1e-6,
+                max_iter=2000000, t1_enable=True, l_min=0.01)
+    print("mixed relax", r)
+    assert r["status"] == 0
+    m = oracle.Mesh(T.topology(), t.n_vert, t.Lx, t.Ly)
+    _, Fo = oracle.energy_forces(m, Xd.cpu().numpy(), p)
+    assert np.abs(Fo).max() < 2e-6          # FP64 forces of the FP32-relaxed state
+
+
+# ------------------------------------------------------------------- adjoint
+
+@pytest.fixture(scope="module")
+def equilibrium(oracle):
+    rng = np.random.default_rng(11)
+    t = g.random_tissue(20, np.sqrt(20.0), rng=rng)
+    p = g.uniform_params(t, P0=3.75)
+    p.lam = rng.uniform(0.05, 0.15, t.n_edge)
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    r = oracle.relax(m, X, p, eta=3e-3, tol=1e-11, patience=1, max_iter=400000,
+                     t1_enable=True, l_min=0.01)
+    assert r["status"] == 0
+    Xt = X + rng.normal(0, 0.05, X.shape)
+    return t, m, X, p, Xt
+
+
+def test_hvp_f64(vtx, oracle, equilibrium):
+    t, m, X, p, Xt = equilibrium
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=X.shape)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    Hv = T.hvp(_dev(X), vtx.Params.from_numpy(p), _dev(v)).cpu().numpy()
+    Hvo = oracle.hvp(m, X, p, v)
+    assert np.abs(Hv - Hvo).max() < 1e-10 * np.abs(Hvo).max()
+
+
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_adjoint_gradient_f64(vtx, oracle, equilibrium, theta):
+    t, m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    go, info_o = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    gg, info = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=_dev(b), theta=theta,
+                            cg_tol=1e-10)
+    assert info["status"] == 0
+    assert abs(info["cg_iters"] - info_o["iters"]) <= 2
+    assert np.abs(gg.cpu().numpy() - go).max() < 1e-7 * np.abs(go).max()
+
+
+def test_ep_gradient_f64(vtx, oracle, equilibrium):
+    t, m, X, p, Xt = equilibrium
+    beta = 0.04
+    go, _ = oracle.ep_grad(m, X, p, Xt, beta, eta=3e-3, tol=1e-12, patience=1, max_iter=400000)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    gg, info = T.param_grad(_dev(X), vtx.Params.from_numpy(p), X_target=_dev(Xt),
+                            method="ep", beta=beta,
+                            ep_relax=dict(eta=3e-3, tol=1e-12, max_iter=400000))
+    assert info["status"] == 0
+    assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+
+
+# ------------------------------------------------------------------- batched
+
+def test_batch_relax_matches_single(vtx):
+    rng = np.random.default_rng(41)
+    tissues, Xs, Ps = [], [], []
+    for n in (64, 150, 90, 300):
+        t = g.random_tissue(n, np.sqrt(n), rng=rng)
+        p = g.uniform_params(t, P0=float(rng.uniform(3.6, 3.9)))
+        p.lam = rng.uniform(0.0, 0.2, t.n_edge)
+        tissues.append(t)
+        Ps.append(p)
+    # single-tissue reference path
+    single = []
+    for t, p in zip(tissues, Ps):
+        T = vtx.Tissue.from_tissue(t)
+        Xd = _dev(t.X)
+        r = T.relax(Xd, vtx.Params.from_numpy(p), mode="f64", eta=3e-3, tol=1e-6,
+                    max_iter=300000, t1_enable=True, l_min=0.01)
+        single.append((r, Xd.cpu().numpy(), T.topology()))
+    Ts = [vtx.Tissue.from_tissue(t) for t in tissues]
+    Xs = [_dev(t.X) for t in tissues]
+    B = vtx.Batch(Ts)
+    res = B.relax(Xs, [vtx.Params.from_numpy(p) for p in Ps], mode="f64", eta=3e-3, tol=1e-6,
+                  max_iter=300000, t1_enable=True, l_min=0.01)
+    for (rs, Xs_ref, he_ref), r, X, T in zip(single, res, Xs, Ts):
+        assert r["status"] == rs["status"] == 0
+        assert (r["iters"], r["n_t1"], r["n_stretch"]) == (rs["iters"], rs["n_t1"], rs["n_stretch"])
+        np.testing.assert_array_equal(T.topology(), he_ref)
+        assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
+        assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9)

@@ -1,0 +1,92 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects invalid tables before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_06896_amd import tissue_gen as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vtx.h")
+LIB = os.path.join(ROOT, "paper_2604_06896_amd", "libvtx.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vtx_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def libvtx():
+    if not os.path.exists(LIB):
+        from paper_2604_06896_amd import build
+        build.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("vtx_energy_forces", "vtx_relax", "vtx_t1", "vtx_param_grad",
+                     "vtx_tissue_create", "vtx_batch_relax", "vtx_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(libvtx):
+    missing = [n for n in declared_functions() if not hasattr(libvtx, n)]
+    assert not missing, missing
+
+
+def _create(libvtx, he, n_vert, n_cell, L=5.0):
+    libvtx.vtx_tissue_create.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                         C.c_double, C.c_double, C.POINTER(C.c_void_p)]
+    libvtx.vtx_last_error.restype = C.c_char_p
+    he = np.ascontiguousarray(he, dtype=np.int32)
+    h = C.c_void_p()
+    rc = libvtx.vtx_tissue_create(he.ctypes.data_as(C.c_void_p), he.shape[0], n_vert, n_cell,
+                                  L, L, C.byref(h))
+    return rc, libvtx.vtx_last_error().decode()
+
+
+@pytest.mark.parametrize("corrupt,code", [
+    ("twin", -2), ("next", -2), ("offset", -2), ("face_offsets", -2), ("self_loop", -2),
+    ("vertex_range", -2), ("sizes", -1),
+])
+def test_invalid_tables_are_rejected(libvtx, corrupt, code):
+    t = g.random_tissue(20, np.sqrt(20.0), seed=3)
+    he = t.he.copy()
+    n_vert, n_cell = t.n_vert, t.n_cell
+    if corrupt == "twin":
+        he[0, 2] = 4
+    elif corrupt == "next":
+        he[0, 1] = he[0, 0]
+    elif corrupt == "offset":
+        he[0, 6] = 2
+    elif corrupt == "face_offsets":
+        # shift the target image of one edge (both half-edges stay twins)
+        h = 0
+        he[h, 6] += 1 if he[h, 6] < 1 else -1
+        he[he[h, 2], 6] = -he[h, 6]
+    elif corrupt == "self_loop":
+        he[0, 4] = he[0, 3]
+    elif corrupt == "vertex_range":
+        he[0, 3] = n_vert + 5
+    elif corrupt == "sizes":
+        n_vert = 0
+    rc, msg = _create(libvtx, he, n_vert, n_cell)
+    assert rc == code, msg
+    assert msg
+
+
+def test_four_valent_vertex_rejected(libvtx):
+    t = g.random_tissue(20, np.sqrt(20.0), seed=4)
+    he = t.he.copy()
+    # relabel the source/target of one vertex as another one: valence 6 and 0
+    v, w = 0, 1
+    he[he[:, 3] == w, 3] = v
+    he[he[:, 4] == w, 4] = v
+    rc, msg = _create(libvtx, he, t.n_vert, t.n_cell)
+    assert rc == -2, msg
