@@ -181,6 +181,23 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he);
 int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
                       double *E_dev, void *F, double *maxf_dev, void *stream);
 
+/* Cell pass alone: per-cell coefficients (cA, cP) = (2 K_A (A - A0),
+ * 2 K_P (P - P0)) at X, i.e. minus the cell pressure and the cortical
+ * tension of each cell (derivatives of E with respect to A and P; Methods,
+ * "Vertex model formulation").  coeffs: device [n_cell][2], float for
+ * VTX_F32 and VTX_MIXED, double for VTX_F64.  Asynchronous. */
+int vtx_cell_coeffs(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                    void *coeffs, void *stream);
+
+/* Vertex pass alone: forces F at X from cell coefficients produced by
+ * vtx_cell_coeffs for the same X and parameters (each 3-valent vertex
+ * gathers its 3 neighbours, 3 cells and 3 edge tensions; no atomics).
+ * F: device [n_vert][2] (element type of X); maxf_dev: device double or
+ * NULL.  vtx_energy_forces is vtx_cell_coeffs followed by this call, plus
+ * the energy.  Asynchronous. */
+int vtx_vertex_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                      const void *coeffs, void *F, double *maxf_dev, void *stream);
+
 /* Per-cell area and perimeter at X (double device arrays [n_cell], either
  * may be NULL).  Asynchronous. */
 int vtx_cell_geometry(vtx_tissue t, int32_t mode, const void *X, double *A_dev,

@@ -199,7 +199,8 @@ void free_tissue(vtx_tissue t) {
     DevTissue &d = t->d;
     void *ptrs[] = {d.he, d.he_edge, d.edge_he, d.row_ptr, d.corner, d.corner_he, d.nsides,
                     d.cell_he, d.star_nb, d.star_cell, d.star_edge, d.star_he, t->w.xbuf,
-                    t->w.cap, t->w.cell_aux, t->w.partials, t->w.partials2, t->w.t1_list,
+                    t->w.cap, t->w.cell_aux, t->w.partials, t->w.partials2, t->w.mpart,
+                    t->w.t1_list,
                     t->w.ctl, t->w.cg, t->w.scal, t->ep_buf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -397,6 +398,7 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
     A((void **)&w.cell_aux, 16 * (size_t)n_cell);
     A((void **)&w.partials, 16 * (size_t)nb);
     A((void **)&w.partials2, 16 * (size_t)nb);
+    A((void **)&w.mpart, 16 * (size_t)nb);
     A((void **)&w.t1_list, 4 * (size_t)t1cap);
     A((void **)&w.ctl, 2 * sizeof(LoopCtl));
     A((void **)&w.cg, 8 * 8 * (size_t)n_vert);
@@ -466,6 +468,20 @@ int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_param
     if (!t || !X || !p || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
     launch_eval(t->d, t->w, mode, X, raw(p), E_dev, F, maxf_dev, (hipStream_t)stream);
     return check_launch("vtx_energy_forces");
+}
+
+int vtx_cell_coeffs(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                    void *coeffs, void *stream) {
+    if (!t || !X || !p || !coeffs || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
+    launch_cell_pass(t->d, t->w, mode, X, raw(p), coeffs, (hipStream_t)stream);
+    return check_launch("vtx_cell_coeffs");
+}
+
+int vtx_vertex_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                      const void *coeffs, void *F, double *maxf_dev, void *stream) {
+    if (!t || !X || !p || !coeffs || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
+    launch_vertex_pass(t->d, t->w, mode, X, raw(p), coeffs, F, maxf_dev, (hipStream_t)stream);
+    return check_launch("vtx_vertex_forces");
 }
 
 int vtx_cell_geometry(vtx_tissue t, int32_t mode, const void *X, double *A_dev, double *P_dev,

@@ -105,12 +105,12 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
             // cell pass
             for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
                 const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
-                M A, P;
-                cell_geom<PosT, M>(
+                PosT A, P;  // in the position precision, as in the grid kernels
+                cell_geom<PosT, PosT>(
                     t, Xc, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P,
-                    o.t1_enable != 0, lmin2, B.t1_list, &s_cnt);
-                st2(cap, c, (M)2 * (M)p.ka(c) * (A - (M)p.a0(c)),
-                    (M)2 * (M)p.kp(c) * (P - (M)p.p0(c)));
+                    o.t1_enable != 0, (PosT)lmin2, B.t1_list, &s_cnt);
+                st2(cap, c, (M)((PosT)2 * p.ka(c) * (A - p.a0(c))),
+                    (M)((PosT)2 * p.kp(c) * (P - p.p0(c))));
             }
             __syncthreads();
             // T1 pass
@@ -185,9 +185,9 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
         const PosT *Xr = (const PosT *)B.X;
         for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
             const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
-            M A, P;
-            cell_geom<PosT, M>(
-                t, Xr, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (M)0,
+            PosT A, P;
+            cell_geom<PosT, PosT>(
+                t, Xr, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
                 nullptr, nullptr);
             const double da = (double)A - (double)p.a0(c), dp = (double)P - (double)p.p0(c);
             e += (double)p.ka(c) * da * da + (double)p.kp(c) * dp * dp;

@@ -23,17 +23,23 @@ __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__rest
                                           bool det, M lmin2, int32_t *list,
                                           unsigned int *count) {
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
-    const int32_t w0 = corner_at(0);
-    const int v0 = id_of(w0);
-    const auto p0 = ld2(X, v0);
+    // The first U corners: ids, then all their positions in flight at once
+    // (rows beyond U sides take the loop below).
+    constexpr int U = 8;
+    int32_t w[U];
+    typename Vec2<PosT>::type q[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) w[k] = corner_at(k < n ? k : 0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) q[k] = ld2(X, id_of(w[k]));
+    const auto p0 = q[0];
+    const int v0 = id_of(w[0]);
     M px = 0, py = 0, a = 0, per = 0;
     int vprev = v0;
-    for (int k = 1; k < n; ++k) {
-        const int32_t w = corner_at(k);
-        const int v = id_of(w);
-        const auto q = ld2(X, v);
-        const M rx = (M)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
-        const M ry = (M)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
+    auto step = [&](int k, int32_t wk, typename Vec2<PosT>::type qk) {
+        const int v = id_of(wk);
+        const M rx = (M)pdiff<PosT>(qk.x, p0.x, ox_of(wk), Lx);
+        const M ry = (M)pdiff<PosT>(qk.y, p0.y, oy_of(wk), Ly);
         const M dx = rx - px, dy = ry - py;
         const M l2 = dx * dx + dy * dy;
         a += px * ry - py * rx;
@@ -45,6 +51,13 @@ __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__rest
         px = rx;
         py = ry;
         vprev = v;
+    };
+#pragma unroll
+    for (int k = 1; k < U; ++k)
+        if (k < n) step(k, w[k], q[k]);
+    for (int k = U; k < n; ++k) {
+        const int32_t wk = corner_at(k);
+        step(k, wk, ld2(X, id_of(wk)));
     }
     const M l2 = px * px + py * py;  // closing edge, corner n-1 -> corner 0
     per += sqrt(l2);
@@ -78,9 +91,7 @@ __device__ __forceinline__ void load_star(const DevTissue &t, const PosT *__rest
                                           int v, Star<PosT, M> &s, PosT &xi, PosT &yi) {
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
     const int nv = t.n_vert;
-    const auto pi = ld2(X, v);
-    xi = pi.x;
-    yi = pi.y;
+    // 1) the star (9 coalesced dword loads) and the own position
     int32_t w[3], c[3], e[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -88,20 +99,34 @@ __device__ __forceinline__ void load_star(const DevTissue &t, const PosT *__rest
         c[k] = t.star_cell[k * nv + v];
         e[k] = t.star_edge[k * nv + v];
     }
+    const auto pi = ld2(X, v);
+    // 2) every gather issued before any is used
+    typename Vec2<PosT>::type q[3];
+    typename Vec2<M>::type cc[3];
+    PosT lam[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int j = id_of(w[k]);
-        s.nb[k] = j;
-        const auto q = ld2(X, j);
-        s.dx[k] = (M)pdiff<PosT>(q.x, pi.x, ox_of(w[k]), Lx);
-        s.dy[k] = (M)pdiff<PosT>(q.y, pi.y, oy_of(w[k]), Ly);
-        const auto cc = ld2(cap, c[k]);
-        s.cA[k] = cc.x;
-        s.cP[k] = cc.y;
-        s.lam[k] = (M)p.lm(e[k]);
+        q[k] = ld2(X, id_of(w[k]));
+        cc[k] = ld2(cap, c[k]);
     }
+    if (p.lam) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lam[k] = p.lam[e[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lam[k] = p.lam_s;
+    }
+    xi = pi.x;
+    yi = pi.y;
+    // 3) arithmetic
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+        s.nb[k] = id_of(w[k]);
+        s.dx[k] = (M)pdiff<PosT>(q[k].x, pi.x, ox_of(w[k]), Lx);
+        s.dy[k] = (M)pdiff<PosT>(q[k].y, pi.y, oy_of(w[k]), Ly);
+        s.cA[k] = cc[k].x;
+        s.cP[k] = cc[k].y;
+        s.lam[k] = (M)lam[k];
         const M l = sqrt(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k]);
         // a zero-length edge contributes its minimum-norm subgradient, 0
         const M inv = l > (M)0 ? (M)1 / l : (M)0;

@@ -61,7 +61,6 @@ struct DevParams {
 // Device control block of an iterative loop (relaxation or CG).  Only the
 // library's kernels touch it; the host reads it between graph launches.
 struct LoopCtl {
-    unsigned long long maxf_bits;  // running max |F| (double bits, >= 0)
     unsigned int arrive;           // blocks of the current launch that finished
     unsigned int arrive2;
     int32_t done;
@@ -87,6 +86,7 @@ struct Workspace {
     double *cell_aux;    // per-cell auxiliaries (HVP: dA, dP), double [n_cell][2]
     double *partials;    // per-block partial sums (double)
     double *partials2;
+    double *mpart;       // per-block max |F| partials
     int32_t *t1_list;    // [n_edge] candidate corner indices
     LoopCtl *ctl;        // device control block
     LoopCtl *ctl_host;   // pinned host mirror
@@ -95,15 +95,29 @@ struct Workspace {
     hipStream_t cap_stream;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  Renumbering blocks so that each
+// XCD gets one contiguous eighth of the work keeps the neighbour gathers of
+// spatially ordered cells and vertices inside one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int per = G / kXcds;
+    if (b >= per * kXcds) return b;
+    return (b % kXcds) * per + b / kXcds;
+}
+
 // ------------------------------------------------------ small device maths
 // xa + w*L - xb with the periodic shift applied exactly: the operand next to
 // the box face is moved by L first (exact by Sterbenz's lemma when it lies
 // within [L/2, 2L]), then two nearby values are subtracted.
+// Written with selects rather than branches so that gathers around it stay
+// in one basic block and can all be in flight together.
 template <typename T>
 __host__ __device__ __forceinline__ T pdiff(T xa, T xb, int w, T L) {
-    if (w > 0) return xa - (xb - L);
-    if (w < 0) return (xa - L) - xb;
-    return xa - xb;
+    const T a = w < 0 ? xa - L : xa;
+    const T b = w > 0 ? xb - L : xb;
+    return a - b;
 }
 
 __device__ __forceinline__ double min_image(double d, double L) {
@@ -157,6 +171,16 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 
 __device__ __forceinline__ double ld_acquire(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of part[0..n) by all threads of one block in a fixed order (each
+// thread a fixed strided subset, then the fixed-order block reduction), so
+// the result does not depend on which block performs it.  Valid in thread 0.
+__device__ __forceinline__ double block_sum_array(const double *part, int n, int stride,
+                                                  double *sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += ld_acquire(part + (int64_t)i * stride);
+    return block_sum(s, sh);
 }
 
 // Called by thread 0 after the block's results are stored: returns true in

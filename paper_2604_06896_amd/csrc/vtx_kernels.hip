@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
     __shared__ int32_t rows[kRowLds];
     __shared__ double sh[kBlock / 64];
     const int nc = t.n_cell;
-    const int c0 = blockIdx.x * kBlock;
+    const int c0 = xcd_block() * kBlock;
     const int c = c0 + threadIdx.x;
     const int cend = min(c0 + kBlock, nc);
     const int base = t.row_ptr[c0], top = t.row_ptr[cend];
@@ -49,18 +49,22 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
     double e = 0.0;
     if (c < nc) {
         const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
-        M A, P;
+        // Area and perimeter in the precision of the positions: the
+        // coefficients cA, cP come from differences (A - A0, P - P0) that
+        // cancel, and in FP32 their rounding (~1e-6 on an edge tension) would
+        // exceed a 1e-6 force tolerance.  The force gather stays in M.
+        PosT A, P;
         if (staged)
-            cell_geom<PosT, M>(
-                t, X, n, [&](int k) { return rows[rb - base + k]; }, rb, A, P, det, lmin2,
-                t1_list, &ctl->t1_count);
+            cell_geom<PosT, PosT>(
+                t, X, n, [&](int k) { return rows[rb - base + k]; }, rb, A, P, det,
+                (PosT)lmin2, t1_list, &ctl->t1_count);
         else
-            cell_geom<PosT, M>(
-                t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, det, lmin2,
+            cell_geom<PosT, PosT>(
+                t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, det, (PosT)lmin2,
                 t1_list, &ctl->t1_count);
-        const M ka = (M)p.ka(c), kp = (M)p.kp(c);
-        const M da = A - (M)p.a0(c), dp = P - (M)p.p0(c);
-        st2(cap, c, (M)2 * ka * da, (M)2 * kp * dp);
+        const PosT ka = p.ka(c), kp = p.kp(c);
+        const PosT da = A - p.a0(c), dp = P - p.p0(c);
+        st2(cap, c, (M)((PosT)2 * ka * da), (M)((PosT)2 * kp * dp));
         if (flags & F_ENERGY)
             e = (double)ka * (double)da * (double)da + (double)kp * (double)dp * (double)dp;
     }
@@ -77,15 +81,17 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
         }
         const double bx = block_sum(sx, sh);
         const double by = block_sum(sy, sh);
+        __shared__ int s_last;
         if (threadIdx.x == 0) {
             npart[2 * blockIdx.x] = bx;
             npart[2 * blockIdx.x + 1] = by;
-            if (last_block(&ctl->arrive2)) {
-                double ax = 0.0, ay = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) {
-                    ax += ld_acquire(npart + 2 * b);
-                    ay += ld_acquire(npart + 2 * b + 1);
-                }
+            s_last = last_block(&ctl->arrive2);
+        }
+        __syncthreads();
+        if (s_last) {
+            const double ax = block_sum_array(npart, gridDim.x, 2, sh);
+            const double ay = block_sum_array(npart + 1, gridDim.x, 2, sh);
+            if (threadIdx.x == 0) {
                 const double nv = (double)t.n_vert;
                 ctl->nudge_mean[0] = ax / nv / nv;
                 ctl->nudge_mean[1] = ay / nv / nv;
@@ -95,11 +101,18 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
 }
 
 // ----------------------------------------------------------------- vertex
+// Grids up to this many blocks finish their reductions in the last block
+// to arrive; larger grids leave per-block partials to k_finish, because one
+// arrival atomic per block on a single address serialises (~25 ns each).
+constexpr int kLastBlockMax = 128;
+
 struct VertexArgs {
     LoopCtl *ctl;
     const double *epart_cell;
     int n_epart_cell;
     double *epart_vert;
+    double *mpart;      // per-block max |F|
+    int finish;         // 1: the last block finishes here; 0: k_finish does
     double *E_out;
     double *maxf_out;
     double eta;
@@ -132,13 +145,17 @@ __device__ __forceinline__ void relax_control(LoopCtl *ctl, double mf, int cur) 
     }
 }
 
+template <int MODE>
+__device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk, double *sh,
+                                                  bool plain);
+
 template <typename PosT, typename M, int MODE>  // MODE 0: evaluate, 1: relaxation step
 __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__restrict__ X,
                                                    PosT *__restrict__ out, DevParams<PosT> p,
                                                    const M *__restrict__ cap, VertexArgs a) {
     if (MODE == 1 && a.ctl->done) return;
     __shared__ double sh[kBlock / 64];
-    const int v = blockIdx.x * kBlock + threadIdx.x;
+    const int v = xcd_block() * kBlock + threadIdx.x;
     double el = 0.0, mf = 0.0;
     if (v < t.n_vert) {
         Star<PosT, M> s;
@@ -178,27 +195,64 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__re
     }
     if (MODE == 1 || a.maxf_out || a.E_out) {
         const double m = block_max(mf, sh);
+        __shared__ int s_last;
         if (threadIdx.x == 0) {
-            atomicMax(&a.ctl->maxf_bits, (unsigned long long)__double_as_longlong(m));
-            if (last_block(&a.ctl->arrive)) {
-                const double mfin = __longlong_as_double(
-                    (long long)__hip_atomic_load(&a.ctl->maxf_bits, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT));
-                a.ctl->maxf_bits = 0ull;
-                if (MODE == 1) {
-                    relax_control(a.ctl, mfin, a.cur);
-                } else {
-                    if (a.maxf_out) *a.maxf_out = mfin;
-                    if (a.E_out) {
-                        double E = 0.0;
-                        for (int b = 0; b < a.n_epart_cell; ++b) E += ld_acquire(a.epart_cell + b);
-                        for (unsigned b = 0; b < gridDim.x; ++b) E += ld_acquire(a.epart_vert + b);
-                        *a.E_out = E;
-                    }
-                }
-            }
+            a.mpart[blockIdx.x] = m;
+            s_last = a.finish ? last_block(&a.ctl->arrive) : 0;
+        }
+        __syncthreads();
+        if (s_last) finish_reductions<MODE>(a, gridDim.x, sh, false);
+    }
+}
+
+// Fixed-order reductions of the per-block partials of one evaluation (or one
+// relaxation step), then the result / the convergence control.  `plain`:
+// the partials were written by an earlier kernel, so ordinary loads see them;
+// otherwise (last block of the same kernel) they are read at device scope.
+template <int MODE>
+__device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk, double *sh,
+                                                  bool plain) {
+    double E = 0.0;
+    if (MODE == 0 && a.E_out) {
+        double s = 0.0;
+        if (plain) {
+            for (int i = threadIdx.x; i < a.n_epart_cell; i += blockDim.x) s += a.epart_cell[i];
+            const double ec = block_sum(s, sh);
+            s = 0.0;
+            for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += a.epart_vert[i];
+            E = ec + block_sum(s, sh);
+        } else {
+            const double ec = block_sum_array(a.epart_cell, a.n_epart_cell, 1, sh);
+            const double ev = block_sum_array(a.epart_vert, nblk, 1, sh);
+            E = ec + ev;
         }
     }
+    double m = 0.0;
+    bool nan = false;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        const double x = plain ? a.mpart[i]
+                               : __hip_atomic_load(a.mpart + i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        m = fmax(m, x);
+        nan |= !(x == x);  // fmax drops NaN; keep it visible
+    }
+    if (nan) m = INFINITY;
+    const double mfin = block_max(m, sh);
+    if (threadIdx.x == 0) {
+        if (MODE == 1) {
+            relax_control(a.ctl, mfin, a.cur);
+        } else {
+            if (a.maxf_out) *a.maxf_out = mfin;
+            if (a.E_out) *a.E_out = E;
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_finish(VertexArgs a, int nblk) {
+    if (MODE == 1 && a.ctl->done) return;
+    __shared__ double sh[1024 / 64];
+    finish_reductions<MODE>(a, nblk, sh, true);
 }
 
 // ---------------------------------------------------------------------- T1
@@ -243,20 +297,20 @@ __global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<P
 //   dA = sum_k grad_k A . v_k,  grad_k A = 1/2 R(r_{k+1} - r_{k-1});
 //   dP = sum_k u_k . (v_{k+1} - v_k).
 // Stored as (2 K_A dA, 2 K_P dP).
-template <typename PosT, typename M>
+template <typename PosT, typename M, typename C = PosT>
 __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__restrict__ X,
                                                      DevParams<PosT> p,
                                                      const double *__restrict__ v,
                                                      M *__restrict__ aux, LoopCtl *ctl) {
     if (ctl && ctl->done) return;
-    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const int c = xcd_block() * kBlock + threadIdx.x;
     if (c >= t.n_cell) return;
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
     const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
     const int32_t w0 = t.corner[rb];
     const int v0 = id_of(w0);
     const auto p0 = ld2(X, v0);
-    auto rel = [&](int k, M &rx, M &ry, M &vx, M &vy) {
+    auto rel = [&](int k, C &rx, C &ry, C &vx, C &vy) {
         const int32_t w = t.corner[rb + k];
         const int vv = id_of(w);
         if (k == 0) {
@@ -264,27 +318,27 @@ __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__
             ry = 0;
         } else {
             const auto q = ld2(X, vv);
-            rx = (M)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
-            ry = (M)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
+            rx = (C)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
+            ry = (C)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
         }
         const auto vq = ld2(v, vv);
-        vx = (M)vq.x;
-        vy = (M)vq.y;
+        vx = (C)vq.x;
+        vy = (C)vq.y;
     };
-    M rpx, rpy, vdum0, vdum1;
+    C rpx, rpy, vdum0, vdum1;
     rel(n - 1, rpx, rpy, vdum0, vdum1);
-    M rcx, rcy, vcx, vcy;
+    C rcx, rcy, vcx, vcy;
     rel(0, rcx, rcy, vcx, vcy);
-    M dA = 0, dP = 0;
+    C dA = 0, dP = 0;
     for (int k = 0; k < n; ++k) {
         const int kn = (k + 1 == n) ? 0 : k + 1;
-        M rnx, rny, vnx, vny;
+        C rnx, rny, vnx, vny;
         rel(kn, rnx, rny, vnx, vny);
-        const M gx = (M)0.5 * (rny - rpy), gy = (M)-0.5 * (rnx - rpx);
+        const C gx = (C)0.5 * (rny - rpy), gy = (C)-0.5 * (rnx - rpx);
         dA += gx * vcx + gy * vcy;
-        const M dx = rnx - rcx, dy = rny - rcy;
-        const M l = sqrt(dx * dx + dy * dy);
-        if (l > (M)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
+        const C dx = rnx - rcx, dy = rny - rcy;
+        const C l = sqrt(dx * dx + dy * dy);
+        if (l > (C)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
         rpx = rcx;
         rpy = rcy;
         rcx = rnx;
@@ -292,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__
         vcx = vnx;
         vcy = vny;
     }
-    st2(aux, c, (M)2 * (M)p.ka(c) * dA, (M)2 * (M)p.kp(c) * dP);
+    st2(aux, c, (M)((C)2 * (C)p.ka(c) * dA), (M)((C)2 * (C)p.kp(c) * dP));
 }
 
 // (H v)_i = sum_k [ T_k w_k - u_k (B_k + B_{k-1}) + 1/2 R(d_k)(G_k - G_{k-1})
@@ -311,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *
                                                        LoopCtl *ctl) {
     if (ctl && ctl->done) return;
     __shared__ double sh[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = xcd_block() * kBlock + threadIdx.x;
     double dot = 0.0;
     if (i < t.n_vert) {
         Star<PosT, M> s;
@@ -348,11 +402,15 @@ __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *
     }
     if (dpart) {
         const double bs = block_sum(dot, sh);
+        __shared__ int s_last;
         if (threadIdx.x == 0) {
             dpart[blockIdx.x] = bs;
-            if (ctl && last_block(&ctl->arrive)) {
-                double pAp = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) pAp += ld_acquire(dpart + b);
+            s_last = ctl ? last_block(&ctl->arrive) : 0;
+        }
+        __syncthreads();
+        if (s_last) {
+            const double pAp = block_sum_array(dpart, gridDim.x, 1, sh);
+            if (threadIdx.x == 0) {
                 ctl->pAp = pAp;
                 if (!(pAp > 0.0)) {
                     ctl->done = 1;
@@ -378,15 +436,17 @@ __global__ __launch_bounds__(kBlock) void k_mean2(const double *__restrict__ a, 
     }
     const double bx = block_sum(sx, sh);
     const double by = block_sum(sy, sh);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = bx;
         part[2 * blockIdx.x + 1] = by;
-        if (last_block(&ctl->arrive2)) {
-            double ax = 0.0, ay = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                ax += ld_acquire(part + 2 * b);
-                ay += ld_acquire(part + 2 * b + 1);
-            }
+        s_last = last_block(&ctl->arrive2);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double ax = block_sum_array(part, gridDim.x, 2, sh);
+        const double ay = block_sum_array(part + 1, gridDim.x, 2, sh);
+        if (threadIdx.x == 0) {
             mean_out[0] = ax / (double)nv;
             mean_out[1] = ay / (double)nv;
         }
@@ -423,11 +483,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const double *__restrict__ b
         rr = rx * rx + ry * ry;
     }
     const double bs = block_sum(rr, sh);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = bs;
-        if (last_block(&ctl->arrive)) {
-            double s = 0.0;
-            for (unsigned k = 0; k < gridDim.x; ++k) s += ld_acquire(part + k);
+        s_last = last_block(&ctl->arrive);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double s = block_sum_array(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
             ctl->rr = s;
             ctl->rr0 = s;
             ctl->rel_res = s > 0.0 ? 1.0 : 0.0;
@@ -460,11 +524,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *__restrict__ x,
         rr = r0 * r0 + r1 * r1;
     }
     const double bs = block_sum(rr, sh);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = bs;
-        if (last_block(&ctl->arrive)) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
+        s_last = last_block(&ctl->arrive);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double s = block_sum_array(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
             ctl->beta_cg = s / ctl->rr;
             ctl->rr = s;
             ctl->cg_iter += 1;
@@ -606,13 +674,15 @@ __global__ __launch_bounds__(kBlock) void k_v2v(DevTissue t, const PosT *X, cons
     }
     if (C_out) {
         const double bs = block_sum(c, sh);
+        __shared__ int s_last;
         if (threadIdx.x == 0) {
             part[blockIdx.x] = bs;
-            if (last_block(&ctl->arrive)) {
-                double s = 0.0;
-                for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
-                *C_out = s / (2.0 * (double)t.n_vert);
-            }
+            s_last = last_block(&ctl->arrive);
+        }
+        __syncthreads();
+        if (s_last) {
+            const double s = block_sum_array(part, gridDim.x, 1, sh);
+            if (threadIdx.x == 0) *C_out = s / (2.0 * (double)t.n_vert);
         }
     }
 }
@@ -628,13 +698,15 @@ __global__ __launch_bounds__(kBlock) void k_dot_pos(const PosT *g, const PosT *X
         c = (double)g[2 * (int64_t)v] * (double)X[2 * (int64_t)v] +
             (double)g[2 * (int64_t)v + 1] * (double)X[2 * (int64_t)v + 1];
     const double bs = block_sum(c, sh);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
         part[blockIdx.x] = bs;
-        if (last_block(&ctl->arrive)) {
-            double s = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += ld_acquire(part + b);
-            *out = s;
-        }
+        s_last = last_block(&ctl->arrive);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double s = block_sum_array(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) *out = s;
     }
 }
 
@@ -650,15 +722,17 @@ __global__ __launch_bounds__(kBlock) void k_mean_pos(const PosT *a, int nv, doub
     }
     const double bx = block_sum(sx, sh);
     const double by = block_sum(sy, sh);
+    __shared__ int s_last;
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = bx;
         part[2 * blockIdx.x + 1] = by;
-        if (last_block(&ctl->arrive2)) {
-            double ax = 0.0, ay = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b) {
-                ax += ld_acquire(part + 2 * b);
-                ay += ld_acquire(part + 2 * b + 1);
-            }
+        s_last = last_block(&ctl->arrive2);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double ax = block_sum_array(part, gridDim.x, 2, sh);
+        const double ay = block_sum_array(part + 1, gridDim.x, 2, sh);
+        if (threadIdx.x == 0) {
             mean_out[0] = ax / (double)nv;
             mean_out[1] = ay / (double)nv;
         }
@@ -698,10 +772,14 @@ static void eval_impl(const DevTissue &t, const Workspace &w, const void *X, con
     a.epart_cell = w.partials;
     a.n_epart_cell = (int)gc;
     a.epart_vert = w.partials2;
+    a.mpart = w.mpart;
+    a.finish = gv <= (unsigned)kLastBlockMax;
     a.E_out = E;
     a.maxf_out = maxf;
     hipLaunchKernelGGL((k_vertex<PosT, M, 0>), dim3(gv), dim3(kBlock), 0, s, t, (const PosT *)X,
                        (PosT *)F, p, (const M *)w.cap, a);
+    if (!a.finish && (E || maxf))
+        hipLaunchKernelGGL((k_finish<0>), dim3(1), dim3(1024), 0, s, a, (int)gv);
 }
 
 void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X,
@@ -709,6 +787,44 @@ void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X
     if (mode == VTX_F32) eval_impl<float, float>(t, w, X, p, E, F, maxf, s);
     else if (mode == VTX_F64) eval_impl<double, double>(t, w, X, p, E, F, maxf, s);
     else eval_impl<double, float>(t, w, X, p, E, F, maxf, s);
+}
+
+template <typename PosT, typename M>
+static void pass_impl(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                      void *coeffs, const void *coeffs_in, void *F, double *maxf, hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    LoopCtl *ectl = w.ctl + 1;
+    if (coeffs)
+        hipLaunchKernelGGL((k_cell<PosT, M>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t,
+                           (const PosT *)X, p, (M *)coeffs, (double *)nullptr, ectl,
+                           (int32_t *)nullptr, (M)0, 0, (const PosT *)nullptr, (double *)nullptr);
+    if (coeffs_in) {
+        const unsigned gv = blocks_for(t.n_vert);
+        VertexArgs a{};
+        a.ctl = ectl;
+        a.maxf_out = maxf;
+        a.mpart = w.mpart;
+        a.finish = gv <= (unsigned)kLastBlockMax;
+        hipLaunchKernelGGL((k_vertex<PosT, M, 0>), dim3(gv), dim3(kBlock), 0, s, t,
+                           (const PosT *)X, (PosT *)F, p, (const M *)coeffs_in, a);
+        if (!a.finish && maxf)
+            hipLaunchKernelGGL((k_finish<0>), dim3(1), dim3(1024), 0, s, a, (int)gv);
+    }
+}
+
+void launch_cell_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                      const ParamsRaw &p, void *coeffs, hipStream_t s) {
+    if (mode == VTX_F32) pass_impl<float, float>(t, w, X, p, coeffs, nullptr, nullptr, nullptr, s);
+    else if (mode == VTX_F64) pass_impl<double, double>(t, w, X, p, coeffs, nullptr, nullptr, nullptr, s);
+    else pass_impl<double, float>(t, w, X, p, coeffs, nullptr, nullptr, nullptr, s);
+}
+
+void launch_vertex_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                        const ParamsRaw &p, const void *coeffs, void *F, double *maxf,
+                        hipStream_t s) {
+    if (mode == VTX_F32) pass_impl<float, float>(t, w, X, p, nullptr, coeffs, F, maxf, s);
+    else if (mode == VTX_F64) pass_impl<double, double>(t, w, X, p, nullptr, coeffs, F, maxf, s);
+    else pass_impl<double, float>(t, w, X, p, nullptr, coeffs, F, maxf, s);
 }
 
 template <typename PosT, typename M>
@@ -736,8 +852,11 @@ static void relax_iter_impl(const DevTissue &t, const Workspace &w, void *Xc, vo
     a.beta = ra.beta;
     a.Xt = ra.X_target;
     a.g_lin = ra.g_lin;
+    a.mpart = w.mpart;
+    a.finish = gv <= (unsigned)kLastBlockMax;
     hipLaunchKernelGGL((k_vertex<PosT, M, 1>), dim3(gv), dim3(kBlock), 0, s, t,
                        (const PosT *)Xc, (PosT *)Xn, p, (const M *)w.cap, a);
+    if (!a.finish) hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(1024), 0, s, a, (int)gv);
 }
 
 void launch_relax_iter(const DevTissue &t, const Workspace &w, int mode, void *Xc, void *Xn,

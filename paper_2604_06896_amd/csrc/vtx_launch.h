@@ -23,6 +23,11 @@ struct RelaxArgs {
 
 void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X,
                  const ParamsRaw &p, double *E, void *F, double *maxf, hipStream_t s);
+void launch_cell_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                      const ParamsRaw &p, void *coeffs, hipStream_t s);
+void launch_vertex_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                        const ParamsRaw &p, const void *coeffs, void *F, double *maxf,
+                        hipStream_t s);
 void launch_relax_iter(const DevTissue &t, const Workspace &w, int mode, void *Xc, void *Xn,
                        int cur, const ParamsRaw &p, const RelaxArgs &ra, hipStream_t s);
 void launch_t1(const DevTissue &t, const Workspace &w, int mode, void *X, const ParamsRaw &p,

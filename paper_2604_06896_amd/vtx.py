@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvtx.so")
+LIB_PATH = os.environ.get("VTX_LIB", os.path.join(HERE, "libvtx.so"))
 
 OK, E_ARG, E_TOPOLOGY, E_CAPACITY, E_HIP, E_NONFINITE = 0, -1, -2, -3, -4, -5
 CONVERGED, NOT_CONVERGED, CG_NEG_CURVATURE, CG_MAXITER = 0, 1, 2, 3
@@ -84,6 +84,8 @@ def lib():
         L.vtx_tissue_get_topology.argtypes = [vp, vp]
         L.vtx_tissue_set_topology.argtypes = [vp, vp]
         L.vtx_energy_forces.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
+        L.vtx_cell_coeffs.argtypes = [vp, i32, vp, P(_Params), vp, vp]
+        L.vtx_vertex_forces.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
         L.vtx_cell_geometry.argtypes = [vp, i32, vp, vp, vp, vp]
         L.vtx_edge_lengths.argtypes = [vp, i32, vp, vp, vp]
         L.vtx_relax.argtypes = [vp, i32, vp, P(_Params), P(_RelaxOpts), P(_RelaxResult), vp]
@@ -238,6 +240,28 @@ class Tissue:
         """Low-overhead variant for timing loops: parameters already marshalled."""
         _check(lib().vtx_energy_forces(self._h, _mode(mode), _ptr(X), C.byref(c_params), _ptr(E),
                                        _ptr(F), _ptr(maxf), _stream()))
+
+    def cell_coeffs(self, X, params, mode="f64"):
+        """Per-cell (cA, cP) = (2K_A(A-A0), 2K_P(P-P0))."""
+        m = self._xcheck(X, mode)
+        p, keep = params.to_c(X.dtype, X.device)
+        dt = torch.float64 if m == F64 else torch.float32
+        out = torch.empty((self.n_cell, 2), dtype=dt, device=X.device)
+        _check(lib().vtx_cell_coeffs(self._h, m, _ptr(X), C.byref(p), _ptr(out), _stream()))
+        return out
+
+    def vertex_forces(self, X, params, coeffs, mode="f64", want_maxf=False):
+        m = self._xcheck(X, mode)
+        p, keep = params.to_c(X.dtype, X.device)
+        F = torch.empty_like(X)
+        mf = torch.empty((), dtype=torch.float64, device=X.device) if want_maxf else None
+        _check(lib().vtx_vertex_forces(self._h, m, _ptr(X), C.byref(p), _ptr(coeffs), _ptr(F),
+                                       _ptr(mf), _stream()))
+        return F, mf
+
+    def vertex_forces_into(self, X, c_params, coeffs, F, mode="f32"):
+        _check(lib().vtx_vertex_forces(self._h, _mode(mode), _ptr(X), C.byref(c_params),
+                                       _ptr(coeffs), _ptr(F), None, _stream()))
 
     def cell_geometry(self, X, mode="f64"):
         m = self._xcheck(X, mode)

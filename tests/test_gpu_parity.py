@@ -149,19 +149,22 @@ def test_t1_pass_bit_exact_topology(vtx, oracle, mode):
 # ---------------------------------------------------------------- relaxation
 
 def test_relax_fixed_iterations_f64(vtx, oracle):
-    """100-cell tissue, P0 = 3.8, no line tension, no T1: 400 GD steps."""
+    """100-cell tissue, P0 = 3.8, no line tension, no T1.  Without T1 this
+    tissue never reaches an equilibrium (edges collapse and GD chatters), and
+    the trajectory is chaotic after ~100 steps (a 1e-15 perturbation grows
+    to 1e-8 by step 100 in the oracle itself), so 50 steps are compared."""
     t, p = g.workload_single_100()
     m = oracle.Mesh.from_tissue(t)
     X = t.X.copy()
-    ro = oracle.relax(m, X, p, eta=1e-2, tol=0.0, patience=1, max_iter=400)
+    ro = oracle.relax(m, X, p, eta=1e-2, tol=0.0, patience=1, max_iter=50)
     T = vtx.Tissue.from_tissue(t)
     Xd = _dev(t.X)
-    r = T.relax(Xd, vtx.Params(P0=3.8, lam=0.0), mode="f64", eta=1e-2, tol=0.0, max_iter=400,
-                chunk=64)
-    assert r["iters"] == ro["iters"] == 400 and r["status"] == 1
+    r = T.relax(Xd, vtx.Params(P0=3.8, lam=0.0), mode="f64", eta=1e-2, tol=0.0, max_iter=50,
+                chunk=16)
+    assert r["iters"] == ro["iters"] == 50 and r["status"] == 1
     assert np.abs(Xd.cpu().numpy() - X).max() < 1e-9
-    assert r["max_f"] == pytest.approx(ro["max_f"], rel=1e-6)
-    assert r["energy"] == pytest.approx(ro["energy"], rel=1e-10)
+    assert r["max_f"] == pytest.approx(ro["max_f"], rel=1e-8)
+    assert r["energy"] == pytest.approx(ro["energy"], rel=1e-12)
 
 
 def test_relax_with_t1_to_equilibrium_f64(vtx, oracle):
@@ -257,31 +260,59 @@ def test_ep_gradient_f64(vtx, oracle, equilibrium):
 
 # ------------------------------------------------------------------- batched
 
-def test_batch_relax_matches_single(vtx):
+def _batch_case(rng, n, P0):
+    t = g.random_tissue(n, np.sqrt(n), rng=rng)
+    p = g.uniform_params(t, P0=P0)
+    p.lam = rng.uniform(0.0, 0.2, t.n_edge)
+    return t, p
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_batch_relax_matches_single(vtx, mode):
+    """Solid tissues (P0 < 3.8; some converge within the iteration cap, some
+    do not yet) plus one fluid tissue (P0 = 3.86) that keeps cycling short
+    edges and stops at max_iter: the persistent batch kernel reproduces the
+    single-tissue path exactly in every case."""
     rng = np.random.default_rng(41)
-    tissues, Xs, Ps = [], [], []
-    for n in (64, 150, 90, 300):
-        t = g.random_tissue(n, np.sqrt(n), rng=rng)
-        p = g.uniform_params(t, P0=float(rng.uniform(3.6, 3.9)))
-        p.lam = rng.uniform(0.0, 0.2, t.n_edge)
-        tissues.append(t)
-        Ps.append(p)
-    # single-tissue reference path
+    cases = [_batch_case(rng, n, P0) for n, P0 in
+             ((64, 3.65), (150, 3.70), (90, 3.63), (300, 3.72), (120, 3.86))]
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=60000, t1_enable=True, l_min=0.01)
     single = []
-    for t, p in zip(tissues, Ps):
+    for t, p in cases:
         T = vtx.Tissue.from_tissue(t)
         Xd = _dev(t.X)
-        r = T.relax(Xd, vtx.Params.from_numpy(p), mode="f64", eta=3e-3, tol=1e-6,
-                    max_iter=300000, t1_enable=True, l_min=0.01)
+        r = T.relax(Xd, vtx.Params.from_numpy(p), mode=mode, **opts)
         single.append((r, Xd.cpu().numpy(), T.topology()))
-    Ts = [vtx.Tissue.from_tissue(t) for t in tissues]
-    Xs = [_dev(t.X) for t in tissues]
+    Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
+    Xs = [_dev(t.X) for t, _ in cases]
     B = vtx.Batch(Ts)
-    res = B.relax(Xs, [vtx.Params.from_numpy(p) for p in Ps], mode="f64", eta=3e-3, tol=1e-6,
-                  max_iter=300000, t1_enable=True, l_min=0.01)
+    res = B.relax(Xs, [vtx.Params.from_numpy(p) for _, p in cases], mode=mode, **opts)
     for (rs, Xs_ref, he_ref), r, X, T in zip(single, res, Xs, Ts):
-        assert r["status"] == rs["status"] == 0
+        print("single", rs, "batch", r)
+        assert r["status"] == rs["status"]
         assert (r["iters"], r["n_t1"], r["n_stretch"]) == (rs["iters"], rs["n_t1"], rs["n_stretch"])
         np.testing.assert_array_equal(T.topology(), he_ref)
         assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
-        assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9)
+        # the single path sums the line energy from FP32 lengths in MIXED mode
+        assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9 if mode == "f64" else 1e-7)
+    st = [r["status"] for r in res]
+    assert st[0] == 0 and st[2] == 0 and st[4] == 1
+
+
+def test_split_passes_equal_full_evaluation(vtx, oracle):
+    t, p = g.workload_single_10k(n_cell=3000, seed=5)
+    T = vtx.Tissue.from_tissue(t)
+    for mode, dt in (("f32", torch.float32), ("f64", torch.float64), ("mixed", torch.float64)):
+        Xd = _dev(t.X, dt)
+        P = vtx.Params.from_numpy(p, dtype=dt)
+        _, F, _ = T.energy_forces(Xd, P, mode=mode)
+        cf = T.cell_coeffs(Xd, P, mode=mode)
+        F2, mf = T.vertex_forces(Xd, P, cf, mode=mode, want_maxf=True)
+        assert torch.equal(F, F2)
+        assert mf.item() == F.abs().max().item()
+    # the coefficients are -pressure and tension: 2K_A(A-A0), 2K_P(P-P0)
+    Xd = _dev(t.X)
+    cf = T.cell_coeffs(Xd, vtx.Params.from_numpy(p), mode="f64").cpu().numpy()
+    A, P_, _ = oracle.cells(oracle.Mesh.from_tissue(t), t.X)
+    np.testing.assert_allclose(cf[:, 0], 2 * p.KA * (A - p.A0), rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(cf[:, 1], 2 * p.KP * (P_ - p.P0), rtol=1e-10, atol=1e-13)
