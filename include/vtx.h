@@ -267,6 +267,18 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
                     const vtx_relax_opts *o, int32_t schedule, int32_t block_threads,
                     vtx_relax_result *res, void *stream);
 
+/* Hypergradients of every tissue of the batch (see vtx_param_grad).
+ * ADJOINT: one persistent launch, one workgroup per tissue running the
+ * whole CG solve and the contraction.  EP_CENTRED: two batched nudged
+ * relaxations (vtx_batch_relax with a per-tissue nudge) and one estimate
+ * launch.  X_star, p, dC_dX, X_target and dC_dtheta are host arrays of n
+ * entries (device pointers inside; dC_dX or X_target may be NULL as for
+ * vtx_param_grad).  Results go to the host array res[n]; synchronises. */
+int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const vtx_params *p,
+                         const double *const *dC_dX, const void *const *X_target,
+                         const vtx_grad_opts *o, double *const *dC_dtheta, int32_t block_threads,
+                         vtx_grad_result *res, void *stream);
+
 /* Message of the last error on the calling thread (never NULL). */
 const char *vtx_last_error(void);
 

@@ -22,6 +22,7 @@ namespace vtx {
 const DevTissue &tissue_dev(vtx_tissue t);
 const Workspace &tissue_ws(vtx_tissue t);
 int64_t tissue_size(vtx_tissue t);
+double *tissue_ep_buf(vtx_tissue t);
 int set_error(int code, const char *msg);
 }  // namespace vtx
 
@@ -29,9 +30,12 @@ struct vtx_batch_s {
     std::vector<vtx_tissue> ts;
     std::vector<int32_t> order;  // tissue indices by descending size
     void *items;                 // device BatchItem[n]
+    void *gitems;                // device GradItem[n]
+    void **xm_list;              // device pointer list (EP minus states)
     int32_t *order_d;
     unsigned int *queue;
     vtx_relax_result *res_d;
+    vtx_grad_result *gres_d;
     hipStream_t cap_stream;
 };
 
@@ -44,6 +48,29 @@ struct BatchItem {
     void *cap;
     int32_t *t1_list;
     ParamsRaw p;
+    // nudge (equilibrium propagation): beta * C with C the v2v cost to Xt or
+    // the linear cost g_lin . X; the mean of grad C is removed
+    const void *Xt;
+    const double *g_lin;
+    double beta;
+};
+
+// One tissue of a batched adjoint: H mu = P b by CG, then the contraction.
+struct GradItem {
+    DevTissue t;
+    const void *X;
+    ParamsRaw p;
+    const double *b;     // dC/dX [n_vert][2]
+    double *cg;          // x, r, q, Aq: 4 x [n_vert][2]
+    void *cap;
+    void *aux;
+    double *g;           // output [n_edge] or [n_cell]
+};
+
+struct GradOpts {
+    double tol;
+    int64_t max_iter;
+    int theta;
 };
 
 struct BatchOpts {
@@ -68,7 +95,189 @@ __device__ __forceinline__ DevParams<PosT> to_dev(const ParamsRaw &r) {
     return p;
 }
 
+// Gradient of the nudge cost at vertex v (v2v, minimum image; or linear).
+template <typename PosT>
+__device__ __forceinline__ void nudge_grad(const BatchItem &B, const PosT *X, int v, double inv_n,
+                                           double &cx, double &cy) {
+    if (B.Xt) {
+        const PosT *Xt = (const PosT *)B.Xt;
+        cx = min_image((double)X[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], B.t.Lx) * inv_n;
+        cy = min_image((double)X[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], B.t.Ly) * inv_n;
+    } else {
+        cx = B.g_lin[2 * (int64_t)v];
+        cy = B.g_lin[2 * (int64_t)v + 1];
+    }
+}
+
 __global__ void k_reset_queue(unsigned int *q) { *q = 0u; }
+
+// Block-wide sum over a strided set, fixed order (thread 0 has the result,
+// broadcast through `bc`).
+__device__ __forceinline__ double bsum_bcast(double v, double *sh, double *bc) {
+    const double r = block_sum(v, sh);
+    if (threadIdx.x == 0) *bc = r;
+    __syncthreads();
+    const double out = *bc;
+    __syncthreads();
+    return out;
+}
+
+// Batched adjoint: one workgroup per tissue runs conjugate gradients on
+// H mu = P b (P removes the per-component mean) with FP64 dots, then the
+// contraction with the mixed derivatives (Methods, "Implicit
+// differentiation (ID)"); same steps as the grid path.
+template <typename PosT, typename M>
+__global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ items,
+                                                   const int32_t *__restrict__ order, int n,
+                                                   unsigned int *queue, GradOpts o,
+                                                   vtx_grad_result *res) {
+    __shared__ double sh[16];
+    __shared__ double s_bc;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int slot = s_item;
+        __syncthreads();
+        if (slot >= n) return;
+        const int idx = order[slot];
+        const GradItem &G = items[idx];
+        const DevTissue t = G.t;
+        const DevParams<PosT> p = to_dev<PosT>(G.p);
+        const PosT *X = (const PosT *)G.X;
+        M *cap = (M *)G.cap;
+        M *aux = (M *)G.aux;
+        const int nv = t.n_vert;
+        double *x = G.cg, *r = G.cg + 2 * (int64_t)nv, *q = G.cg + 4 * (int64_t)nv,
+               *Aq = G.cg + 6 * (int64_t)nv;
+        // cell coefficients at X*
+        for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
+            const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
+            PosT A, P;
+            cell_geom<PosT, PosT>(
+                t, X, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
+                nullptr, nullptr);
+            st2(cap, c, (M)((PosT)2 * p.ka(c) * (A - p.a0(c))),
+                (M)((PosT)2 * p.kp(c) * (P - p.p0(c))));
+        }
+        // r = P b, q = r, x = 0
+        double sx = 0.0, sy = 0.0;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            sx += G.b[2 * (int64_t)v];
+            sy += G.b[2 * (int64_t)v + 1];
+        }
+        const double mbx = bsum_bcast(sx, sh, &s_bc) / (double)nv;
+        const double mby = bsum_bcast(sy, sh, &s_bc) / (double)nv;
+        double rr = 0.0;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const double r0 = G.b[2 * (int64_t)v] - mbx, r1 = G.b[2 * (int64_t)v + 1] - mby;
+            r[2 * (int64_t)v] = r0;
+            r[2 * (int64_t)v + 1] = r1;
+            q[2 * (int64_t)v] = r0;
+            q[2 * (int64_t)v + 1] = r1;
+            x[2 * (int64_t)v] = 0.0;
+            x[2 * (int64_t)v + 1] = 0.0;
+            rr += r0 * r0 + r1 * r1;
+        }
+        rr = bsum_bcast(rr, sh, &s_bc);
+        const double rr0 = rr;
+        int status = rr0 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
+        int64_t it = 0;
+        while (status == VTX_CG_MAXITER && it < o.max_iter) {
+            if (sqrt(rr) <= o.tol * sqrt(rr0)) {
+                status = VTX_CONVERGED;
+                break;
+            }
+            for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
+                hvp_cell_one<PosT, M>(t, X, p, q, aux, c);
+            __syncthreads();
+            double d = 0.0;
+            for (int v = threadIdx.x; v < nv; v += blockDim.x)
+                d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, q, Aq, v);
+            const double pAp = bsum_bcast(d, sh, &s_bc);
+            if (!(pAp > 0.0)) {
+                status = VTX_CG_NEG_CURVATURE;
+                break;
+            }
+            const double al = rr / pAp;
+            double rn = 0.0;
+            for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+                const int64_t k = 2 * (int64_t)v;
+                x[k] += al * q[k];
+                x[k + 1] += al * q[k + 1];
+                const double r0 = r[k] - al * Aq[k], r1 = r[k + 1] - al * Aq[k + 1];
+                r[k] = r0;
+                r[k + 1] = r1;
+                rn += r0 * r0 + r1 * r1;
+            }
+            rn = bsum_bcast(rn, sh, &s_bc);
+            const double be = rn / rr;
+            rr = rn;
+            ++it;
+            for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+                const int64_t k = 2 * (int64_t)v;
+                q[k] = r[k] + be * q[k];
+                q[k + 1] = r[k + 1] + be * q[k + 1];
+            }
+            __syncthreads();
+        }
+        if (status == VTX_CG_MAXITER && sqrt(rr) <= o.tol * sqrt(rr0)) status = VTX_CONVERGED;
+        // project the solution to zero mean
+        sx = 0.0;
+        sy = 0.0;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            sx += x[2 * (int64_t)v];
+            sy += x[2 * (int64_t)v + 1];
+        }
+        const double mxx = bsum_bcast(sx, sh, &s_bc) / (double)nv;
+        const double mxy = bsum_bcast(sy, sh, &s_bc) / (double)nv;
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            x[2 * (int64_t)v] -= mxx;
+            x[2 * (int64_t)v + 1] -= mxy;
+        }
+        __syncthreads();
+        if (o.theta == VTX_THETA_LAMBDA)
+            for (int e = threadIdx.x; e < t.n_edge; e += blockDim.x)
+                G.g[e] = contract_lambda_one<PosT>(t, X, x, e);
+        else
+            for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
+                G.g[c] = contract_p0_one<PosT>(t, X, p, x, c);
+        if (threadIdx.x == 0) {
+            vtx_grad_result gr{};
+            gr.cg_iters = it;
+            gr.cg_rel_res = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+            gr.status = status;
+            res[idx] = gr;
+        }
+        __syncthreads();
+    }
+}
+
+// Centred EP estimate from the two nudged states, one workgroup per tissue.
+template <typename PosT>
+__global__ __launch_bounds__(1024) void k_batch_ep(const GradItem *__restrict__ items, int n,
+                                                   const void *const *Xm_list, double beta,
+                                                   int theta) {
+    for (int idx = blockIdx.x; idx < n; idx += gridDim.x) {
+        const GradItem &G = items[idx];
+        const DevTissue t = G.t;
+        const PosT *Xp = (const PosT *)G.X;
+        const PosT *Xm = (const PosT *)Xm_list[idx];
+        if (theta == VTX_THETA_LAMBDA) {
+            for (int e = threadIdx.x; e < t.n_edge; e += blockDim.x)
+                G.g[e] = (edge_len_one<PosT>(t, Xp, e) - edge_len_one<PosT>(t, Xm, e)) / beta;
+        } else {
+            const DevParams<PosT> p = to_dev<PosT>(G.p);
+            PosOverride<PosT> none{-1, -1, 0, 0, 0, 0};
+            for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
+                double a, pp, pm;
+                cell_walk<PosT>(t, Xp, t.cell_he[c], none, a, pp);
+                cell_walk<PosT>(t, Xm, t.cell_he[c], none, a, pm);
+                G.g[c] = -2.0 * (double)p.kp(c) * (pp - pm) / beta;
+            }
+        }
+    }
+}
 
 template <typename PosT, typename M>
 __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restrict__ items,
@@ -81,6 +290,7 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
     __shared__ double sh[16];
     __shared__ unsigned int s_cnt;
     __shared__ int s_item, s_done, s_changed, s_rbuf;
+    __shared__ double s_mean[2];
     const M lmin2 = (M)(o.l_min * o.l_min * (1.0 + 1e-4));
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
@@ -134,6 +344,27 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
                 if (s_changed) rebuild_rows_block(t, scan);
                 __syncthreads();
             }
+            // mean of the nudge gradient over the vertices
+            const double inv_n = 1.0 / (double)t.n_vert;
+            double mx = 0.0, my = 0.0;
+            if (B.beta != 0.0) {
+                double sx = 0.0, sy = 0.0;
+                for (int v = threadIdx.x; v < t.n_vert; v += blockDim.x) {
+                    double cx, cy;
+                    nudge_grad<PosT>(B, Xc, v, inv_n, cx, cy);
+                    sx += cx;
+                    sy += cy;
+                }
+                const double bx = block_sum(sx, sh);
+                const double by = block_sum(sy, sh);
+                if (threadIdx.x == 0) {
+                    s_mean[0] = bx * inv_n;
+                    s_mean[1] = by * inv_n;
+                }
+                __syncthreads();
+                mx = s_mean[0];
+                my = s_mean[1];
+            }
             // vertex pass with the step
             double mf = 0.0;
             for (int v = threadIdx.x; v < t.n_vert; v += blockDim.x) {
@@ -142,10 +373,16 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
                 load_star<PosT, M>(t, Xc, p, cap, v, s, xi, yi);
                 M fx, fy;
                 star_force<PosT, M>(s, fx, fy);
-                mf = fmax(mf, fmax(fabs((double)fx), fabs((double)fy)));
-                if (!(fx == fx) || !(fy == fy)) mf = INFINITY;
-                st2(Xn, v, (PosT)((double)xi + o.eta * (double)fx),
-                    (PosT)((double)yi + o.eta * (double)fy));
+                double gx = fx, gy = fy;
+                if (B.beta != 0.0) {
+                    double cx, cy;
+                    nudge_grad<PosT>(B, Xc, v, inv_n, cx, cy);
+                    gx -= B.beta * (cx - mx);
+                    gy -= B.beta * (cy - my);
+                }
+                mf = fmax(mf, fmax(fabs(gx), fabs(gy)));
+                if (!(gx == gx) || !(gy == gy)) mf = INFINITY;
+                st2(Xn, v, (PosT)((double)xi + o.eta * gx), (PosT)((double)yi + o.eta * gy));
             }
             const double m = block_max(mf, sh);
             if (threadIdx.x == 0) {
@@ -198,6 +435,18 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
             const double dy = pdiff<double>((double)Xr[2 * (int64_t)r[HG] + 1], (double)Xr[2 * (int64_t)r[HS] + 1], r[HOY], t.Ly);
             e += (double)p.lm(k) * sqrt(dx * dx + dy * dy);
         }
+        if (B.beta != 0.0)
+            for (int v = threadIdx.x; v < t.n_vert; v += blockDim.x) {
+                if (B.Xt) {
+                    const PosT *Xt = (const PosT *)B.Xt;
+                    const double dx = min_image((double)Xr[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
+                    const double dy = min_image((double)Xr[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
+                    e += B.beta * (dx * dx + dy * dy) * 0.5 / (double)t.n_vert;
+                } else {
+                    e += B.beta * (B.g_lin[2 * (int64_t)v] * (double)Xr[2 * (int64_t)v] +
+                                   B.g_lin[2 * (int64_t)v + 1] * (double)Xr[2 * (int64_t)v + 1]);
+                }
+            }
         const double E = block_sum(e, sh);
         if (threadIdx.x == 0) {
             vtx_relax_result r;
@@ -215,6 +464,93 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
 
 }  // namespace vtx
 
+namespace {
+
+bool mode_ok(int m) { return m == VTX_F32 || m == VTX_F64 || m == VTX_MIXED; }
+
+ParamsRaw raw_params(const vtx_params &q) {
+    return ParamsRaw{q.KA, q.A0, q.KP, q.P0, q.lam, q.KA_s, q.A0_s, q.KP_s, q.P0_s, q.lam_s};
+}
+
+int hip_fail(hipError_t e) { return set_error(VTX_E_HIP, hipGetErrorString(e)); }
+
+// Capture (queue reset + one persistent launch) as a graph and run it.
+template <typename Launch>
+int run_graph(vtx_batch b, hipStream_t s, Launch launch) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, b->cap_stream, b->queue);
+    launch(b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    return e == hipSuccess ? VTX_OK : hip_fail(e);
+}
+
+int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
+                    const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
+                    double beta, int block_threads, vtx_relax_result *res, hipStream_t s) {
+    const int n = (int)b->ts.size();
+    std::vector<BatchItem> items(n);
+    for (int i = 0; i < n; ++i) {
+        if (!X[i]) return set_error(VTX_E_ARG, "null X in batch");
+        const Workspace &w = tissue_ws(b->ts[i]);
+        BatchItem &it = items[i];
+        it.t = tissue_dev(b->ts[i]);
+        it.X = X[i];
+        it.xbuf = w.xbuf;
+        it.cap = w.cap;
+        it.t1_list = w.t1_list;
+        it.p = raw_params(p[i]);
+        it.Xt = Xt ? Xt[i] : nullptr;
+        it.g_lin = g_lin ? g_lin[i] : nullptr;
+        it.beta = beta;
+        if (beta != 0.0 && !it.Xt && !it.g_lin) return set_error(VTX_E_ARG, "nudge without a cost");
+    }
+    hipError_t e = hipMemcpyAsync(b->items, items.data(), sizeof(BatchItem) * n,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    BatchOpts bo{o->eta, o->tol, o->l_min, o->l_new, o->patience, o->max_iter, o->t1_enable};
+    const BatchItem *it = (const BatchItem *)b->items;
+    int rc = run_graph(b, s, [&](hipStream_t cs) {
+        const dim3 grid(n), block(block_threads);
+        if (mode == VTX_F32)
+            hipLaunchKernelGGL((k_batch_relax<float, float>), grid, block, 0, cs, it, b->order_d,
+                               n, b->queue, bo, b->res_d);
+        else if (mode == VTX_F64)
+            hipLaunchKernelGGL((k_batch_relax<double, double>), grid, block, 0, cs, it,
+                               b->order_d, n, b->queue, bo, b->res_d);
+        else
+            hipLaunchKernelGGL((k_batch_relax<double, float>), grid, block, 0, cs, it, b->order_d,
+                               n, b->queue, bo, b->res_d);
+    });
+    if (rc) return rc;
+    e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i)
+        if (res[i].status == VTX_E_NONFINITE) {
+            res[i].status = VTX_NOT_CONVERGED;
+            return set_error(VTX_E_NONFINITE, "non-finite forces in a batched relaxation");
+        }
+    return VTX_OK;
+}
+
+int check_relax_opts(const vtx_relax_opts *o) {
+    if (!(o->eta > 0) || !(o->tol >= 0) || o->patience < 1 || o->max_iter < 1)
+        return set_error(VTX_E_ARG, "bad relax options");
+    if (o->t1_enable && !(o->l_min > 0 && o->l_new > 0))
+        return set_error(VTX_E_ARG, "T1 needs l_min > 0 and l_new > 0");
+    return VTX_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
@@ -229,15 +565,18 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
         return tissue_size(b->ts[a]) > tissue_size(b->ts[c]);
     });
     hipError_t e = hipMalloc(&b->items, sizeof(BatchItem) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->gitems, sizeof(GradItem) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->xm_list, sizeof(void *) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->order_d, sizeof(int32_t) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->queue, sizeof(unsigned int));
     if (e == hipSuccess) e = hipMalloc((void **)&b->res_d, sizeof(vtx_relax_result) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->gres_d, sizeof(vtx_grad_result) * n);
     if (e == hipSuccess)
         e = hipMemcpy(b->order_d, b->order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         vtx_batch_destroy(b);
-        return set_error(VTX_E_HIP, hipGetErrorString(e));
+        return hip_fail(e);
     }
     *out = b;
     return VTX_OK;
@@ -246,10 +585,9 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
 int vtx_batch_destroy(vtx_batch b) {
     if (!b) return set_error(VTX_E_ARG, "null batch");
     (void)hipDeviceSynchronize();
-    if (b->items) (void)hipFree(b->items);
-    if (b->order_d) (void)hipFree(b->order_d);
-    if (b->queue) (void)hipFree(b->queue);
-    if (b->res_d) (void)hipFree(b->res_d);
+    void *ptrs[] = {b->items, b->gitems, b->xm_list, b->order_d, b->queue, b->res_d, b->gres_d};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return VTX_OK;
@@ -259,66 +597,117 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
                     const vtx_relax_opts *o, int32_t schedule, int32_t block_threads,
                     vtx_relax_result *res, void *stream) {
     if (!b || !X || !p || !o || !res) return set_error(VTX_E_ARG, "null argument");
-    if (mode != VTX_F32 && mode != VTX_F64 && mode != VTX_MIXED)
-        return set_error(VTX_E_ARG, "bad precision mode");
+    if (!mode_ok(mode)) return set_error(VTX_E_ARG, "bad precision mode");
     if (schedule != 0) return set_error(VTX_E_ARG, "only schedule 0 (block per tissue) exists");
     if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
         return set_error(VTX_E_ARG, "block_threads must be 256, 512 or 1024");
     if (o->beta != 0.0) return set_error(VTX_E_ARG, "batched relaxation takes no nudge");
-    if (!(o->eta > 0) || !(o->tol >= 0) || o->patience < 1 || o->max_iter < 1)
-        return set_error(VTX_E_ARG, "bad relax options");
-    if (o->t1_enable && !(o->l_min > 0 && o->l_new > 0))
-        return set_error(VTX_E_ARG, "T1 needs l_min > 0 and l_new > 0");
-    const int n = (int)b->ts.size();
-    std::vector<BatchItem> items(n);
-    for (int i = 0; i < n; ++i) {
-        if (!X[i]) return set_error(VTX_E_ARG, "null X in batch");
-        const Workspace &w = tissue_ws(b->ts[i]);
-        items[i].t = tissue_dev(b->ts[i]);
-        items[i].X = X[i];
-        items[i].xbuf = w.xbuf;
-        items[i].cap = w.cap;
-        items[i].t1_list = w.t1_list;
-        const vtx_params &q = p[i];
-        items[i].p = ParamsRaw{q.KA, q.A0, q.KP, q.P0, q.lam, q.KA_s, q.A0_s, q.KP_s, q.P0_s, q.lam_s};
-    }
+    int rc = check_relax_opts(o);
+    if (rc) return rc;
+    return batch_relax_run(b, mode, X, p, o, nullptr, nullptr, 0.0, block_threads, res,
+                           (hipStream_t)stream);
+}
+
+int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const vtx_params *p,
+                         const double *const *dC_dX, const void *const *X_target,
+                         const vtx_grad_opts *o, double *const *dC_dtheta, int32_t block_threads,
+                         vtx_grad_result *res, void *stream) {
+    if (!b || !X_star || !p || !o || !dC_dtheta || !res) return set_error(VTX_E_ARG, "null argument");
+    if (!mode_ok(mode)) return set_error(VTX_E_ARG, "bad precision mode");
+    if (o->theta != VTX_THETA_LAMBDA && o->theta != VTX_THETA_P0)
+        return set_error(VTX_E_ARG, "unknown theta selector");
+    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return set_error(VTX_E_ARG, "block_threads must be 256, 512 or 1024");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(b->items, items.data(), sizeof(BatchItem) * n,
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return set_error(VTX_E_HIP, hipGetErrorString(e));
-    BatchOpts bo{o->eta, o->tol, o->l_min, o->l_new, o->patience, o->max_iter, o->t1_enable};
-    // reset of the queue + the persistent launch, captured once as a graph
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return set_error(VTX_E_HIP, hipGetErrorString(e));
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, b->cap_stream, b->queue);
-    const BatchItem *it = (const BatchItem *)b->items;
-    const dim3 grid(n), block(block_threads);
-    if (mode == VTX_F32)
-        hipLaunchKernelGGL((k_batch_relax<float, float>), grid, block, 0, b->cap_stream, it,
-                           b->order_d, n, b->queue, bo, b->res_d);
-    else if (mode == VTX_F64)
-        hipLaunchKernelGGL((k_batch_relax<double, double>), grid, block, 0, b->cap_stream, it,
-                           b->order_d, n, b->queue, bo, b->res_d);
-    else
-        hipLaunchKernelGGL((k_batch_relax<double, float>), grid, block, 0, b->cap_stream, it,
-                           b->order_d, n, b->queue, bo, b->res_d);
-    e = hipStreamEndCapture(b->cap_stream, &g);
-    if (e != hipSuccess) return set_error(VTX_E_HIP, hipGetErrorString(e));
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(ge, s);
+    const int n = (int)b->ts.size();
+    std::vector<GradItem> items(n);
+    for (int i = 0; i < n; ++i) {
+        if (!X_star[i] || !dC_dtheta[i]) return set_error(VTX_E_ARG, "null pointer in batch");
+        const Workspace &w = tissue_ws(b->ts[i]);
+        GradItem &g = items[i];
+        g.t = tissue_dev(b->ts[i]);
+        g.X = X_star[i];
+        g.p = raw_params(p[i]);
+        g.b = dC_dX ? dC_dX[i] : nullptr;
+        g.cg = w.cg;
+        g.cap = w.cap;
+        g.aux = w.cell_aux;
+        g.g = dC_dtheta[i];
+    }
+    hipError_t e;
+    if (o->method == VTX_GRAD_ADJOINT) {
+        if (!dC_dX) return set_error(VTX_E_ARG, "the adjoint needs dC_dX");
+        for (int i = 0; i < n; ++i)
+            if (!dC_dX[i]) return set_error(VTX_E_ARG, "null dC_dX in batch");
+        if (!(o->cg_tol > 0) || o->cg_max_iter < 1) return set_error(VTX_E_ARG, "bad CG options");
+        e = hipMemcpyAsync(b->gitems, items.data(), sizeof(GradItem) * n, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e);
+        GradOpts go{o->cg_tol, o->cg_max_iter, o->theta};
+        const GradItem *gi = (const GradItem *)b->gitems;
+        int rc = run_graph(b, s, [&](hipStream_t cs) {
+            const dim3 grid(n), block(block_threads);
+            if (mode == VTX_F32)
+                hipLaunchKernelGGL((k_batch_cg<float, float>), grid, block, 0, cs, gi, b->order_d,
+                                   n, b->queue, go, b->gres_d);
+            else if (mode == VTX_F64)
+                hipLaunchKernelGGL((k_batch_cg<double, double>), grid, block, 0, cs, gi,
+                                   b->order_d, n, b->queue, go, b->gres_d);
+            else
+                hipLaunchKernelGGL((k_batch_cg<double, float>), grid, block, 0, cs, gi, b->order_d,
+                                   n, b->queue, go, b->gres_d);
+        });
+        if (rc) return rc;
+        e = hipMemcpyAsync(res, b->gres_d, sizeof(vtx_grad_result) * n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e == hipSuccess ? VTX_OK : hip_fail(e);
+    }
+    if (o->method != VTX_GRAD_EP_CENTRED) return set_error(VTX_E_ARG, "unknown method");
+    if (!(o->beta != 0.0)) return set_error(VTX_E_ARG, "EP needs beta != 0");
+    if (o->ep_relax.t1_enable) return set_error(VTX_E_ARG, "EP relaxations cannot use T1");
+    int rc = check_relax_opts(&o->ep_relax);
+    if (rc) return rc;
+    if (!X_target && !dC_dX) return set_error(VTX_E_ARG, "EP needs X_target or dC_dX");
+    const size_t esz = (mode == VTX_F32 ? sizeof(float) : sizeof(double));
+    std::vector<void *> Xp(n), Xm(n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t nv = tissue_dev(b->ts[i]).n_vert;
+        char *base = (char *)tissue_ep_buf(b->ts[i]);
+        Xp[i] = base;
+        Xm[i] = base + 16 * (size_t)nv;
+        e = hipMemcpyAsync(Xp[i], X_star[i], 2 * nv * esz, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(Xm[i], X_star[i], 2 * nv * esz, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    std::vector<vtx_relax_result> rp(n), rm(n);
+    rc = batch_relax_run(b, mode, Xp.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
+                         0.5 * o->beta, block_threads, rp.data(), s);
+    if (rc) return rc;
+    rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
+                         -0.5 * o->beta, block_threads, rm.data(), s);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) items[i].X = Xp[i];
+    e = hipMemcpyAsync(b->gitems, items.data(), sizeof(GradItem) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(b->xm_list, Xm.data(), sizeof(void *) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    const GradItem *gi = (const GradItem *)b->gitems;
+    const dim3 grid(n), block(256);
+    if (mode == VTX_F32)
+        hipLaunchKernelGGL((k_batch_ep<float>), grid, block, 0, s, gi, n,
+                           (const void *const *)b->xm_list, o->beta, o->theta);
+    else
+        hipLaunchKernelGGL((k_batch_ep<double>), grid, block, 0, s, gi, n,
+                           (const void *const *)b->xm_list, o->beta, o->theta);
+    e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (ge) (void)hipGraphExecDestroy(ge);
-    if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return set_error(VTX_E_HIP, hipGetErrorString(e));
-    for (int i = 0; i < n; ++i)
-        if (res[i].status == VTX_E_NONFINITE) {
-            res[i].status = VTX_NOT_CONVERGED;
-            return set_error(VTX_E_NONFINITE, "non-finite forces in a batched relaxation");
-        }
+    if (e != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < n; ++i) {
+        vtx_grad_result r{};
+        r.ep_plus = rp[i];
+        r.ep_minus = rm[i];
+        r.status = std::max(rp[i].status, rm[i].status);
+        res[i] = r;
+    }
     return VTX_OK;
 }
 

@@ -516,4 +516,150 @@ __device__ __forceinline__ int rebuild_rows_block(const DevTissue &t, int32_t *s
     return bad;
 }
 
+// ------------------------------------------------------------------- HVP
+// Directional derivatives of one cell's area and perimeter along v, in the
+// precision of the positions:
+//   dA = sum_k grad_k A . v_k,  grad_k A = 1/2 R(r_{k+1} - r_{k-1});
+//   dP = sum_k u_k . (v_{k+1} - v_k)  (zero-length edges contribute 0).
+// Stored as (G, B) = (2 K_A dA, 2 K_P dP).
+template <typename PosT, typename M>
+__device__ __forceinline__ void hvp_cell_one(const DevTissue &t, const PosT *__restrict__ X,
+                                             const DevParams<PosT> &p,
+                                             const double *__restrict__ v, M *__restrict__ aux,
+                                             int c) {
+    using C = PosT;
+    const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
+    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    const int32_t w0 = t.corner[rb];
+    const auto p0 = ld2(X, id_of(w0));
+    auto rel = [&](int k, C &rx, C &ry, C &vx, C &vy) {
+        const int32_t w = t.corner[rb + k];
+        const int vv = id_of(w);
+        if (k == 0) {
+            rx = 0;
+            ry = 0;
+        } else {
+            const auto q = ld2(X, vv);
+            rx = (C)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
+            ry = (C)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
+        }
+        const auto vq = ld2(v, vv);
+        vx = (C)vq.x;
+        vy = (C)vq.y;
+    };
+    C rpx, rpy, vd0, vd1;
+    rel(n - 1, rpx, rpy, vd0, vd1);
+    C rcx, rcy, vcx, vcy;
+    rel(0, rcx, rcy, vcx, vcy);
+    C dA = 0, dP = 0;
+    for (int k = 0; k < n; ++k) {
+        const int kn = (k + 1 == n) ? 0 : k + 1;
+        C rnx, rny, vnx, vny;
+        rel(kn, rnx, rny, vnx, vny);
+        const C gx = (C)0.5 * (rny - rpy), gy = (C)-0.5 * (rnx - rpx);
+        dA += gx * vcx + gy * vcy;
+        const C dx = rnx - rcx, dy = rny - rcy;
+        const C l = sqrt(dx * dx + dy * dy);
+        if (l > (C)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
+        rpx = rcx;
+        rpy = rcy;
+        rcx = rnx;
+        rcy = rny;
+        vcx = vnx;
+        vcy = vny;
+    }
+    st2(aux, c, (M)((C)2 * (C)p.ka(c) * dA), (M)((C)2 * (C)p.kp(c) * dP));
+}
+
+// (H v)_i = sum_k [ T_k w_k - u_k (B_k + B_{k-1}) + 1/2 R(d_k)(G_k - G_{k-1})
+//                   + 1/2 R(v_{j_k} - v_i)(cA_k - cA_{k-1}) ]
+// with w_k = (I - u_k u_k^T)(v_i - v_{j_k}) / l_k, T_k the edge tension
+// (lambda_k + cP_k + cP_{k-1}), G = 2K_A dA and B = 2K_P dP of the sector
+// cells.  Writes (Hv)_i and returns v_i . (Hv)_i.
+template <typename PosT, typename M>
+__device__ __forceinline__ double hvp_vertex_one(const DevTissue &t, const PosT *__restrict__ X,
+                                                 const DevParams<PosT> &p,
+                                                 const M *__restrict__ cap,
+                                                 const M *__restrict__ aux,
+                                                 const double *__restrict__ v,
+                                                 double *__restrict__ Hv, int i) {
+    Star<PosT, M> s;
+    PosT xi, yi;
+    load_star<PosT, M>(t, X, p, cap, i, s, xi, yi);
+    const auto vi = ld2(v, i);
+    M G[3], B[3], vx[3], vy[3];
+    const int nv = t.n_vert;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const auto g = ld2(aux, t.star_cell[k * nv + i]);
+        G[k] = g.x;
+        B[k] = g.y;
+        const auto vj = ld2(v, s.nb[k]);
+        vx[k] = (M)(vj.x - vi.x);  // v_{j_k} - v_i
+        vy[k] = (M)(vj.y - vi.y);
+    }
+    M hx = 0, hy = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int km = (k + 2) % 3;
+        const M T = s.lam[k] + s.cP[k] + s.cP[km];
+        const M du = -(vx[k] * s.ux[k] + vy[k] * s.uy[k]);  // (v_i - v_j) . u
+        const M wx = (-vx[k] - du * s.ux[k]) * s.inv[k];
+        const M wy = (-vy[k] - du * s.uy[k]) * s.inv[k];
+        const M Bs = B[k] + B[km];
+        const M dG = (M)0.5 * (G[k] - G[km]);
+        const M dC = (M)0.5 * (s.cA[k] - s.cA[km]);
+        hx += T * wx - s.ux[k] * Bs + dG * s.dy[k] + dC * vy[k];
+        hy += T * wy - s.uy[k] * Bs - dG * s.dx[k] - dC * vx[k];
+    }
+    st2(Hv, i, (double)hx, (double)hy);
+    return vi.x * (double)hx + vi.y * (double)hy;
+}
+
+// ------------------------------------------------------------ contractions
+// theta = lambda:  g_e = -(d2E/dX dlambda_e) . mu = -u_e . (mu_tgt - mu_src)
+template <typename PosT>
+__device__ __forceinline__ double contract_lambda_one(const DevTissue &t, const PosT *X,
+                                                      const double *mu, int e) {
+    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
+    const int s = r[HS], q = r[HG];
+    const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+    const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+    const double l = sqrt(dx * dx + dy * dy);
+    return l > 0.0 ? -(dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
+                       dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l
+                   : 0.0;
+}
+
+// theta = P0:  g_c = -(d2E/dX dP0_c) . mu = 2 K_P grad P_c . mu
+template <typename PosT>
+__device__ __forceinline__ double contract_p0_one(const DevTissue &t, const PosT *X,
+                                                  const DevParams<PosT> &p, const double *mu,
+                                                  int c) {
+    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    double dP = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int h = t.corner_he[rb + k];
+        const int32_t *r = t.he + 8 * (int64_t)h;
+        const int s = r[HS], q = r[HG];
+        const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+        const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+        const double l = sqrt(dx * dx + dy * dy);
+        if (l > 0.0)
+            dP += (dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
+                   dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l;
+    }
+    return 2.0 * (double)p.kp(c) * dP;
+}
+
+// Edge length in double from positions of any precision.
+template <typename PosT>
+__device__ __forceinline__ double edge_len_one(const DevTissue &t, const PosT *X, int e) {
+    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
+    const int s = r[HS], q = r[HG];
+    const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
+    const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
+    return sqrt(dx * dx + dy * dy);
+}
+
 }  // namespace vtx

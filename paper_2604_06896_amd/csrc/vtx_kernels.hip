@@ -205,6 +205,24 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__re
     }
 }
 
+// Per-thread sum of p[threadIdx.x + j * blockDim.x] in a fixed order, with
+// eight independent loads in flight per step (a plain `s += p[i]` loop waits
+// for each load before the next).
+__device__ __forceinline__ double strided_sum(const double *p, int n) {
+    double s = 0.0;
+    for (int base = 0; base < n; base += 8 * (int)blockDim.x) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+            x[u] = i < n ? p[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    return s;
+}
+
 // Fixed-order reductions of the per-block partials of one evaluation (or one
 // relaxation step), then the result / the convergence control.  `plain`:
 // the partials were written by an earlier kernel, so ordinary loads see them;
@@ -214,13 +232,9 @@ __device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk,
                                                   bool plain) {
     double E = 0.0;
     if (MODE == 0 && a.E_out) {
-        double s = 0.0;
         if (plain) {
-            for (int i = threadIdx.x; i < a.n_epart_cell; i += blockDim.x) s += a.epart_cell[i];
-            const double ec = block_sum(s, sh);
-            s = 0.0;
-            for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += a.epart_vert[i];
-            E = ec + block_sum(s, sh);
+            const double ec = block_sum(strided_sum(a.epart_cell, a.n_epart_cell), sh);
+            E = ec + block_sum(strided_sum(a.epart_vert, nblk), sh);
         } else {
             const double ec = block_sum_array(a.epart_cell, a.n_epart_cell, 1, sh);
             const double ev = block_sum_array(a.epart_vert, nblk, 1, sh);
@@ -229,12 +243,27 @@ __device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk,
     }
     double m = 0.0;
     bool nan = false;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-        const double x = plain ? a.mpart[i]
-                               : __hip_atomic_load(a.mpart + i, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        m = fmax(m, x);
-        nan |= !(x == x);  // fmax drops NaN; keep it visible
+    if (plain) {
+        for (int base = 0; base < nblk; base += 8 * (int)blockDim.x) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+                x[u] = i < nblk ? a.mpart[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                m = fmax(m, x[u]);
+                nan |= !(x[u] == x[u]);  // fmax drops NaN; keep it visible
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+            const double x = __hip_atomic_load(a.mpart + i, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            m = fmax(m, x);
+            nan |= !(x == x);
+        }
     }
     if (nan) m = INFINITY;
     const double mfin = block_max(m, sh);
@@ -293,11 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<P
 }
 
 // -------------------------------------------------------------------- HVP
-// Directional derivatives of each cell's area and perimeter along v:
-//   dA = sum_k grad_k A . v_k,  grad_k A = 1/2 R(r_{k+1} - r_{k-1});
-//   dP = sum_k u_k . (v_{k+1} - v_k).
-// Stored as (2 K_A dA, 2 K_P dP).
-template <typename PosT, typename M, typename C = PosT>
+template <typename PosT, typename M>
 __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__restrict__ X,
                                                      DevParams<PosT> p,
                                                      const double *__restrict__ v,
@@ -305,55 +330,9 @@ __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__
     if (ctl && ctl->done) return;
     const int c = xcd_block() * kBlock + threadIdx.x;
     if (c >= t.n_cell) return;
-    const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
-    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
-    const int32_t w0 = t.corner[rb];
-    const int v0 = id_of(w0);
-    const auto p0 = ld2(X, v0);
-    auto rel = [&](int k, C &rx, C &ry, C &vx, C &vy) {
-        const int32_t w = t.corner[rb + k];
-        const int vv = id_of(w);
-        if (k == 0) {
-            rx = 0;
-            ry = 0;
-        } else {
-            const auto q = ld2(X, vv);
-            rx = (C)pdiff<PosT>(q.x, p0.x, ox_of(w), Lx);
-            ry = (C)pdiff<PosT>(q.y, p0.y, oy_of(w), Ly);
-        }
-        const auto vq = ld2(v, vv);
-        vx = (C)vq.x;
-        vy = (C)vq.y;
-    };
-    C rpx, rpy, vdum0, vdum1;
-    rel(n - 1, rpx, rpy, vdum0, vdum1);
-    C rcx, rcy, vcx, vcy;
-    rel(0, rcx, rcy, vcx, vcy);
-    C dA = 0, dP = 0;
-    for (int k = 0; k < n; ++k) {
-        const int kn = (k + 1 == n) ? 0 : k + 1;
-        C rnx, rny, vnx, vny;
-        rel(kn, rnx, rny, vnx, vny);
-        const C gx = (C)0.5 * (rny - rpy), gy = (C)-0.5 * (rnx - rpx);
-        dA += gx * vcx + gy * vcy;
-        const C dx = rnx - rcx, dy = rny - rcy;
-        const C l = sqrt(dx * dx + dy * dy);
-        if (l > (C)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
-        rpx = rcx;
-        rpy = rcy;
-        rcx = rnx;
-        rcy = rny;
-        vcx = vnx;
-        vcy = vny;
-    }
-    st2(aux, c, (M)((C)2 * (C)p.ka(c) * dA), (M)((C)2 * (C)p.kp(c) * dP));
+    hvp_cell_one<PosT, M>(t, X, p, v, aux, c);
 }
 
-// (H v)_i = sum_k [ T_k w_k - u_k (B_k + B_{k-1}) + 1/2 R(d_k)(G_k - G_{k-1})
-//                   + 1/2 R(v_{j_k} - v_i)(cA_k - cA_{k-1}) ]
-// with w_k = (I - u_k u_k^T)(v_i - v_{j_k}) / l_k, T_k the edge tension,
-// G = 2K_A dA and B = 2K_P dP of the sector cells.  Also accumulates the
-// FP64 dot v . Hv and, in CG, alpha = rr / (p . Ap).
 template <typename PosT, typename M>
 __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *__restrict__ X,
                                                        DevParams<PosT> p,
@@ -367,39 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *
     __shared__ double sh[kBlock / 64];
     const int i = xcd_block() * kBlock + threadIdx.x;
     double dot = 0.0;
-    if (i < t.n_vert) {
-        Star<PosT, M> s;
-        PosT xi, yi;
-        load_star<PosT, M>(t, X, p, cap, i, s, xi, yi);
-        const auto vi = ld2(v, i);
-        M G[3], B[3], vx[3], vy[3];
-        const int nv = t.n_vert;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const auto g = ld2(aux, t.star_cell[k * nv + i]);
-            G[k] = g.x;
-            B[k] = g.y;
-            const auto vj = ld2(v, s.nb[k]);
-            vx[k] = (M)(vj.x - vi.x);  // v_{j_k} - v_i
-            vy[k] = (M)(vj.y - vi.y);
-        }
-        M hx = 0, hy = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int km = (k + 2) % 3;
-            const M T = s.lam[k] + s.cP[k] + s.cP[km];
-            const M du = -(vx[k] * s.ux[k] + vy[k] * s.uy[k]);  // (v_i - v_j) . u
-            const M wx = (-vx[k] - du * s.ux[k]) * s.inv[k];
-            const M wy = (-vy[k] - du * s.uy[k]) * s.inv[k];
-            const M Bs = B[k] + B[km];
-            const M dG = (M)0.5 * (G[k] - G[km]);
-            const M dC = (M)0.5 * (s.cA[k] - s.cA[km]);
-            hx += T * wx - s.ux[k] * Bs + dG * s.dy[k] + dC * vy[k];
-            hy += T * wy - s.uy[k] * Bs - dG * s.dx[k] - dC * vx[k];
-        }
-        st2(Hv, i, (double)hx, (double)hy);
-        dot = vi.x * (double)hx + vi.y * (double)hy;
-    }
+    if (i < t.n_vert) dot = hvp_vertex_one<PosT, M>(t, X, p, cap, aux, v, Hv, i);
     if (dpart) {
         const double bs = block_sum(dot, sh);
         __shared__ int s_last;
@@ -561,43 +508,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(const double *__restrict__ r,
 }
 
 // ------------------------------------------------------------ contractions
-// theta = lambda:  g_e = -(d2E/dX dlambda_e) . mu = -u_e . (mu_tgt - mu_src)
 template <typename PosT>
 __global__ __launch_bounds__(kBlock) void k_contract_lambda(DevTissue t, const PosT *X,
                                                             const double *mu, double *g) {
     const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= t.n_edge) return;
-    const int32_t *r = t.he + 8 * (int64_t)t.edge_he[e];
-    const int s = r[HS], q = r[HG];
-    const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
-    const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
-    const double l = sqrt(dx * dx + dy * dy);
-    g[e] = l > 0.0 ? -(dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
-                       dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l
-                   : 0.0;
+    if (e < t.n_edge) g[e] = contract_lambda_one<PosT>(t, X, mu, e);
 }
 
-// theta = P0:  g_c = -(d2E/dX dP0_c) . mu = 2 K_P grad P_c . mu
 template <typename PosT>
 __global__ __launch_bounds__(kBlock) void k_contract_p0(DevTissue t, const PosT *X,
                                                         DevParams<PosT> p, const double *mu,
                                                         double *g) {
     const int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= t.n_cell) return;
-    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
-    double dP = 0.0;
-    for (int k = 0; k < n; ++k) {
-        const int h = t.corner_he[rb + k];
-        const int32_t *r = t.he + 8 * (int64_t)h;
-        const int s = r[HS], q = r[HG];
-        const double dx = pdiff<double>((double)X[2 * (int64_t)q], (double)X[2 * (int64_t)s], r[HOX], t.Lx);
-        const double dy = pdiff<double>((double)X[2 * (int64_t)q + 1], (double)X[2 * (int64_t)s + 1], r[HOY], t.Ly);
-        const double l = sqrt(dx * dx + dy * dy);
-        if (l > 0.0)
-            dP += (dx * (mu[2 * (int64_t)q] - mu[2 * (int64_t)s]) +
-                   dy * (mu[2 * (int64_t)q + 1] - mu[2 * (int64_t)s + 1])) / l;
-    }
-    g[c] = 2.0 * (double)p.kp(c) * dP;
+    if (c < t.n_cell) g[c] = contract_p0_one<PosT>(t, X, p, mu, c);
 }
 
 template <typename PosT>

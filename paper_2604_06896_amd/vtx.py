@@ -99,6 +99,8 @@ def lib():
             L.vtx_batch_destroy.argtypes = [vp]
             L.vtx_batch_relax.argtypes = [vp, i32, P(vp), P(_Params), P(_RelaxOpts), i32, i32,
                                           P(_RelaxResult), vp]
+            L.vtx_batch_param_grad.argtypes = [vp, i32, P(vp), P(_Params), P(vp), P(vp),
+                                               P(_GradOpts), P(vp), i32, P(_GradResult), vp]
         _lib = L
     return _lib
 
@@ -372,3 +374,40 @@ class Batch:
         _check(lib().vtx_batch_relax(self._h, m, xs, cps, C.byref(o), int(schedule),
                                      int(block_threads), res, _stream()))
         return [r.as_dict() for r in res]
+
+    def param_grad(self, Xs, params_list, dC_dX=None, X_target=None, method="adjoint",
+                   theta="lambda", mode="f64", cg_tol=1e-8, cg_max_iter=100000, beta=1e-3,
+                   ep_relax=None, block_threads=256):
+        """Hypergradients of every tissue in one batched launch sequence."""
+        m = _mode(mode)
+        n = len(self.tissues)
+        keep = []
+        cps = (_Params * n)()
+        for k, (X, pr) in enumerate(zip(Xs, params_list)):
+            if X.dtype != pos_dtype(m) or not X.is_contiguous():
+                raise ValueError("bad X dtype/layout")
+            cp, kp = pr.to_c(X.dtype, X.device)
+            keep.append(kp)
+            cps[k] = cp
+        th = THETA_LAMBDA if theta == "lambda" else THETA_P0
+        outs = [torch.empty(t.n_edge if th == THETA_LAMBDA else t.n_cell, dtype=torch.float64,
+                            device=X.device) for t, X in zip(self.tissues, Xs)]
+        xs = (C.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        gs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        db = None
+        if dC_dX is not None:
+            dC_dX = [d.to(dtype=torch.float64).contiguous() for d in dC_dX]
+            keep.append(dC_dX)
+            db = (C.c_void_p * n)(*[d.data_ptr() for d in dC_dX])
+        xt = None
+        if X_target is not None:
+            xt = (C.c_void_p * n)(*[x.data_ptr() for x in X_target])
+        meth = GRAD_ADJOINT if method == "adjoint" else GRAD_EP_CENTRED
+        ro = relax_opts(**(ep_relax or {}))
+        o = _GradOpts(meth, th, float(cg_tol), int(cg_max_iter), float(beta), ro)
+        res = (_GradResult * n)()
+        _check(lib().vtx_batch_param_grad(self._h, m, xs, cps, db, xt, C.byref(o), gs,
+                                          int(block_threads), res, _stream()))
+        infos = [dict(cg_iters=r.cg_iters, cg_rel_res=r.cg_rel_res, status=r.status,
+                      ep_plus=r.ep_plus.as_dict(), ep_minus=r.ep_minus.as_dict()) for r in res]
+        return outs, infos

@@ -316,3 +316,110 @@ def test_split_passes_equal_full_evaluation(vtx, oracle):
     A, P_, _ = oracle.cells(oracle.Mesh.from_tissue(t), t.X)
     np.testing.assert_allclose(cf[:, 0], 2 * p.KA * (A - p.A0), rtol=1e-10, atol=1e-13)
     np.testing.assert_allclose(cf[:, 1], 2 * p.KP * (P_ - p.P0), rtol=1e-10, atol=1e-13)
+
+
+# --------------------------------------------------- batched hypergradients
+
+@pytest.fixture(scope="module")
+def small_equilibria(oracle):
+    out = []
+    for seed in (11, 12, 13):
+        rng = np.random.default_rng(seed)
+        t = g.random_tissue(20, np.sqrt(20.0), rng=rng)
+        p = g.uniform_params(t, P0=3.75)
+        p.lam = rng.uniform(0.05, 0.15, t.n_edge)
+        m = oracle.Mesh.from_tissue(t)
+        X = t.X.copy()
+        r = oracle.relax(m, X, p, eta=3e-3, tol=1e-11, patience=1, max_iter=400000,
+                         t1_enable=True, l_min=0.01)
+        assert r["status"] == 0
+        Xt = X + rng.normal(0, 0.05, X.shape)
+        out.append((t, m, X, p, Xt))
+    return out
+
+
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, theta):
+    Ts, Xs, Ps, bs, refs = [], [], [], [], []
+    for t, m, X, p, Xt in small_equilibria:
+        T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+        _, b = oracle.v2v(m, X, Xt)
+        go, _ = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10)
+        gs, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=_dev(b), theta=theta,
+                             cg_tol=1e-10)
+        Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); bs.append(_dev(b))
+        refs.append((go, gs.cpu().numpy()))
+    B = vtx.Batch(Ts)
+    outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10)
+    for (go, gsingle), gb, inf in zip(refs, outs, infos):
+        assert inf["status"] == 0
+        gb = gb.cpu().numpy()
+        assert np.abs(gb - gsingle).max() < 1e-9 * np.abs(go).max()
+        assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
+
+
+def test_batch_ep_matches_single(vtx, oracle, small_equilibria):
+    beta = 0.04
+    ep = dict(eta=3e-3, tol=1e-12, max_iter=400000)
+    Ts, Xs, Ps, Xts, refs = [], [], [], [], []
+    for t, m, X, p, Xt in small_equilibria:
+        T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+        gs, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), X_target=_dev(Xt), method="ep",
+                             beta=beta, ep_relax=ep)
+        Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); Xts.append(_dev(Xt))
+        refs.append(gs.cpu().numpy())
+    B = vtx.Batch(Ts)
+    outs, infos = B.param_grad(Xs, Ps, X_target=Xts, method="ep", beta=beta, ep_relax=ep)
+    for gsingle, gb, inf in zip(refs, outs, infos):
+        assert inf["status"] == 0
+        assert inf["ep_plus"]["iters"] > 1
+        assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-9 * np.abs(gsingle).max()
+
+
+# ------------------------------------------------------------- autograd
+
+@pytest.mark.parametrize("method", ["adjoint", "ep"])
+def test_autograd_equilibrium_gradient(vtx, oracle, small_equilibria, method):
+    from paper_2604_06896_amd.autograd import equilibrium
+    t, m, X, p, Xt = small_equilibria[0]
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    theta = torch.as_tensor(p.lam, dtype=torch.float64, device="cuda").requires_grad_(True)
+    prm = vtx.Params(KA=1.0, A0=1.0, KP=1.0, P0=3.75)
+    grad_kw = dict(cg_tol=1e-11) if method == "adjoint" else \
+        dict(method="ep", beta=1e-2, ep_relax=dict(eta=3e-3, tol=1e-13, max_iter=400000))
+    Xs = equilibrium(theta, _dev(X), T, prm, which="lambda", mode="f64",
+                     relax=dict(eta=3e-3, tol=1e-11, max_iter=400000), grad=grad_kw)
+    Xt_d = _dev(Xt)
+    loss = ((Xs - Xt_d) ** 2).sum() / (2 * t.n_vert)
+    loss.backward()
+    _, b = oracle.v2v(m, Xs.detach().cpu().numpy(), Xt)
+    go, _ = oracle.adjoint_grad(m, Xs.detach().cpu().numpy(), p, b, tol=1e-11)
+    err = np.abs(theta.grad.cpu().numpy() - go).max() / np.abs(go).max()
+    print(method, "relative error vs oracle adjoint", err)
+    assert err < (1e-7 if method == "adjoint" else 1e-3)
+
+
+def test_gradient_matches_library_finite_differences(vtx, small_equilibria):
+    """Central differences of the relaxed v2v cost, all on the GPU (FP64
+    relaxations from X* without T1), along 4 random directions."""
+    t, m, X, p, Xt = small_equilibria[1]
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    Xd, Xtd = _dev(X), _dev(Xt)
+
+    def cost(lam):
+        Xr = Xd.clone()
+        r = T.relax(Xr, vtx.Params(P0=3.75, lam=_dev(lam)), mode="f64", eta=3e-3, tol=1e-12,
+                    max_iter=1000000)
+        assert r["status"] == 0
+        C, _ = T.v2v(Xr, Xtd)
+        return C.item()
+
+    _, b = T.v2v(Xd, Xtd)
+    gg, info = T.param_grad(Xd, vtx.Params.from_numpy(p), dC_dX=b, cg_tol=1e-12)
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        d = rng.normal(size=t.n_edge)
+        d /= np.linalg.norm(d)
+        h = 1e-3
+        fd = (cost(p.lam + h * d) - cost(p.lam - h * d)) / (2 * h)
+        assert gg.cpu().numpy() @ d == pytest.approx(fd, rel=2e-3, abs=1e-9)
