@@ -70,6 +70,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cell", type=int, default=1000000)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the batched relaxation and hypergradient measurements")
+    ap.add_argument("--batch-tissues", type=int, default=512)
+    ap.add_argument("--batch-max-iter", type=int, default=200000)
+    ap.add_argument("--grad-tissues", type=int, default=64)
+    ap.add_argument("--plain-sample", type=int, default=2)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate "
                          "hardware traffic counters")
@@ -207,6 +213,20 @@ def main():
                          f"({dt:.1f} s, one host thread)"}
         log(f"oracle: {n} evaluations in {dt:.1f}s")
 
+    secondary = None
+    if not args.no_secondary:
+        from paper_2604_06896_amd import suite
+        del F2, coeffs
+        torch.cuda.empty_cache()
+        secondary = {}
+        w0 = time.perf_counter()
+        secondary["batched_relax"] = suite.batched_relax(
+            n_tissue=args.batch_tissues, max_iter=args.batch_max_iter,
+            plain_sample=args.plain_sample, block_threads=1024, log=log)
+        secondary["param_gradients"] = suite.param_gradients(
+            n_tissue=args.grad_tissues, plain_sample=args.plain_sample, log=log)
+        log(f"secondary measurements took {time.perf_counter() - w0:.1f}s")
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -232,6 +252,7 @@ def main():
                      "cell_pass": {"achieved": c_gbs, "bytes_per_launch": cb,
                                    "us_per_launch": c_ms * 1e3}},
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,154 @@
+"""Secondary measurements of the batched rows (used by bench.py).
+
+batched_relax: the 512-tissue workload (N ~ U{64..4096}, one P0 ~ U[3.6,3.9]
+per tissue, lambda ~ U[0,0.2]) relaxed with T1 (l_min 0.01) towards
+max |F| < 1e-6 in one persistent launch, against the single-tissue path
+(captured graph chunks) on a sample of the same tissues.
+
+param_gradients: tissues of 1000 cells, P0 = 3.75, hidden tensions lambda*
+and initial tensions theta0 ~ U[0.05,0.15]; targets and predictions are
+relaxed with T1 (batched); dC/dtheta of the v2v cost at the predictions by
+the adjoint (CG tol 1e-8, FP64) and by centred EP (beta = 1e-3), batched
+(one launch sequence for all tissues) against the single-tissue calls.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import tissue_gen as g
+from . import vtx as V
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def batched_relax(n_tissue=512, n_max=4096, max_iter=200000, plain_sample=4, seed=401,
+                  mode="mixed", eta=3e-3, block_threads=256, t1=True, log=print):
+    work = g.workload_batch(seed=seed, n_tissue=n_tissue, n_max=n_max)
+    dt = V.pos_dtype(mode)
+    Ts = [V.Tissue.from_tissue(t) for t, _ in work]
+    Ps = [V.Params(KA=1.0, A0=1.0, KP=1.0, P0=float(p.P0[0]),
+                   lam=torch.as_tensor(p.lam, dtype=dt, device="cuda")) for _, p in work]
+    opts = dict(eta=eta, tol=1e-6, max_iter=max_iter, t1_enable=t1, l_min=0.01)
+    Xs = [torch.as_tensor(t.X, dtype=dt, device="cuda") for t, _ in work]
+    B = V.Batch(Ts)
+    _sync()
+    t0 = time.perf_counter()
+    res = B.relax(Xs, Ps, mode=mode, block_threads=block_threads, **opts)
+    _sync()
+    tb = time.perf_counter() - t0
+    iters = np.array([r["iters"] for r in res])
+    nv = np.array([t.n_vert for t, _ in work])
+    conv = np.array([r["status"] == 0 for r in res])
+    n_t1 = np.array([r["n_t1"] for r in res])
+    n_st = np.array([r["n_stretch"] for r in res])
+    log(f"batched relax: {n_tissue} tissues in {tb:.2f}s, {conv.sum()} converged, "
+        f"iterations median {int(np.median(iters))} max {iters.max()}, "
+        f"T1 total {n_t1.sum()}, stretches total {n_st.sum()} (max {n_st.max()})")
+    # plain path on a sample (same options, fresh handles and positions)
+    rng = np.random.default_rng(0)
+    sample = rng.choice(n_tissue, size=min(plain_sample, n_tissue), replace=False)
+    tp = 0.0
+    same = True
+    for i in sample:
+        t, p = work[i]
+        T = V.Tissue.from_tissue(t)
+        X = torch.as_tensor(t.X, dtype=dt, device="cuda")
+        _sync()
+        t0 = time.perf_counter()
+        r = T.relax(X, Ps[i], mode=mode, **opts)
+        _sync()
+        tp += time.perf_counter() - t0
+        same &= (r["iters"], r["n_t1"], r["status"]) == (res[i]["iters"], res[i]["n_t1"],
+                                                         res[i]["status"])
+    # extrapolate the plain time by vertex-iterations of the sample
+    vi_sample = float((nv[sample] * iters[sample]).sum())
+    vi_all = float((nv * iters).sum())
+    t_plain = tp * vi_all / vi_sample if vi_sample > 0 else float("nan")
+    log(f"plain relax: sample of {len(sample)} in {tp:.2f}s -> {t_plain:.1f}s extrapolated")
+    return {"tissues": n_tissue, "mode": mode, "max_iter": max_iter,
+            "converged": int(conv.sum()), "iters_median": int(np.median(iters)),
+            "iters_max": int(iters.max()), "batched_s": tb,
+            "batched_tissues_per_s": n_tissue / tb,
+            "batched_vertex_iters_per_s": vi_all / tb,
+            "plain_sample": len(sample), "plain_sample_s": tp,
+            "plain_extrapolated_s": t_plain, "speedup": t_plain / tb,
+            "plain_matches_batched_on_sample": bool(same)}
+
+
+def param_gradients(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000, plain_sample=8,
+                    log=print):
+    work = g.workload_inverse(seed=seed, n_tissue=n_tissue, n_cell=n_cell)
+    Ts_t = [V.Tissue.from_tissue(t) for t, _, _ in work]
+    Ts = [V.Tissue.from_tissue(t) for t, _, _ in work]
+    dev = "cuda"
+
+    def prm(p):
+        return V.Params(KA=1.0, A0=1.0, KP=1.0, P0=3.75,
+                        lam=torch.as_tensor(p.lam, dtype=torch.float64, device=dev))
+    ropts = dict(eta=3e-3, tol=1e-6, max_iter=relax_max_iter, t1_enable=True, l_min=0.01)
+    Xt = [torch.as_tensor(t.X, dtype=torch.float64, device=dev) for t, _, _ in work]
+    Xs = [torch.as_tensor(t.X, dtype=torch.float64, device=dev) for t, _, _ in work]
+    Pt = [prm(ps) for _, ps, _ in work]
+    Pi = [prm(pi) for _, _, pi in work]
+    _sync()
+    t0 = time.perf_counter()
+    rt = V.Batch(Ts_t).relax(Xt, Pt, mode="f64", **ropts)
+    rs = V.Batch(Ts).relax(Xs, Pi, mode="f64", **ropts)
+    _sync()
+    t_setup = time.perf_counter() - t0
+    conv = sum(r["status"] == 0 for r in rs) + sum(r["status"] == 0 for r in rt)
+    log(f"inverse workload: {2 * n_tissue} relaxations in {t_setup:.1f}s, {conv} converged")
+    b = [T.v2v(X, Y)[1] for T, X, Y in zip(Ts, Xs, Xt)]
+    B = V.Batch(Ts)
+    out = {"tissues": n_tissue, "n_cell": n_cell, "params_per_tissue": Ts[0].n_edge,
+           "setup_relax_s": t_setup, "relaxations_converged": int(conv)}
+    # adjoint, batched
+    _sync()
+    t0 = time.perf_counter()
+    gb, ib = B.param_grad(Xs, Pi, dC_dX=b, cg_tol=1e-8, cg_max_iter=100000)
+    _sync()
+    tb = time.perf_counter() - t0
+    # adjoint, plain
+    t0 = time.perf_counter()
+    gp = []
+    for T, X, P_, bb in zip(Ts, Xs, Pi, b):
+        gg, _ = T.param_grad(X, P_, dC_dX=bb, cg_tol=1e-8, cg_max_iter=100000)
+        gp.append(gg)
+    _sync()
+    tp = time.perf_counter() - t0
+    diff = max(float((x - y).abs().max() / y.abs().max()) for x, y in zip(gb, gp))
+    cg = [i["cg_iters"] for i in ib]
+    st = [i["status"] for i in ib]
+    log(f"adjoint: batched {tb * 1e3:.1f} ms, plain {tp * 1e3:.1f} ms, CG iters median "
+        f"{int(np.median(cg))}, statuses {sorted(set(st))}, max rel diff {diff:.2e}")
+    out["adjoint"] = {"batched_s": tb, "plain_s": tp,
+                      "batched_grads_per_s": n_tissue / tb, "plain_grads_per_s": n_tissue / tp,
+                      "speedup": tp / tb, "cg_iters_median": int(np.median(cg)),
+                      "cg_iters_max": int(max(cg)),
+                      "converged": int(sum(s == 0 for s in st)),
+                      "batched_vs_plain_max_rel_diff": diff}
+    # EP, batched and plain (beta = 1e-3, FP64 nudged relaxations)
+    ep = dict(eta=3e-3, tol=1e-10, max_iter=relax_max_iter)
+    _sync()
+    t0 = time.perf_counter()
+    ge, ie = B.param_grad(Xs, Pi, X_target=Xt, method="ep", beta=1e-3, ep_relax=ep)
+    _sync()
+    te = time.perf_counter() - t0
+    n_plain = max(1, min(plain_sample, n_tissue))
+    t0 = time.perf_counter()
+    for T, X, P_, Y in list(zip(Ts, Xs, Pi, Xt))[:n_plain]:
+        T.param_grad(X, P_, X_target=Y, method="ep", beta=1e-3, ep_relax=ep)
+    _sync()
+    tep = (time.perf_counter() - t0) * n_tissue / n_plain
+    rel = [float((x - y).abs().max() / y.abs().max()) for x, y in zip(ge, gb)]
+    log(f"EP: batched {te:.2f}s, plain {tep:.2f}s (extrapolated from {n_plain}), "
+        f"EP vs adjoint max rel diff median {np.median(rel):.2e}")
+    out["ep"] = {"beta": 1e-3, "batched_s": te, "plain_s_extrapolated": tep,
+                 "plain_sample": n_plain, "batched_grads_per_s": n_tissue / te,
+                 "speedup": tep / te, "vs_adjoint_rel_diff_median": float(np.median(rel))}
+    return out
