@@ -59,7 +59,7 @@ ParamsRaw raw(const vtx_params *p) {
 
 // Host copy of the staged layouts.
 struct Staged {
-    std::vector<int32_t> he_edge, edge_he, row_ptr, corner, corner_he, nsides, cell_he;
+    std::vector<int32_t> he_edge, edge_he, row_ptr, row_cap, corner, corner_he, nsides, cell_he;
     std::vector<int32_t> star_nb, star_cell, star_edge, star_he;
 };
 
@@ -134,8 +134,13 @@ int validate_and_stage(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t 
         S.nsides[c] = (int32_t)n;
         S.row_ptr[c + 1] = S.row_ptr[c] + (int32_t)n;
     }
-    S.corner.assign(n_he, 0);
-    S.corner_he.assign(n_he, 0);
+    S.row_cap.assign(S.nsides.begin(), S.nsides.end());
+    // corner rows: compact rows, room to re-compact them with kRowSlack spare
+    // slots each, then a relocation pool of n_he + 1024 slots
+    const int64_t cap_total = 2 * n_he + kRowSlack * n_cell + 1024;
+    if (cap_total >= INT32_MAX) return fail(VTX_E_CAPACITY, "tissue too large");
+    S.corner.assign(cap_total, 0);
+    S.corner_he.assign(cap_total, 0);
     for (int64_t c = 0; c < n_cell; ++c) {
         int64_t h = S.cell_he[c], k = S.row_ptr[c];
         int wx = 0, wy = 0;
@@ -197,7 +202,8 @@ int upload_into(int32_t *dst, const std::vector<int32_t> &src) {
 void free_tissue(vtx_tissue t) {
     if (!t) return;
     DevTissue &d = t->d;
-    void *ptrs[] = {d.he, d.he_edge, d.edge_he, d.row_ptr, d.corner, d.corner_he, d.nsides,
+    void *ptrs[] = {d.he, d.he_edge, d.edge_he, d.row_ptr, d.row_cap, d.pool_top, d.corner,
+                    d.corner_he, d.nsides,
                     d.cell_he, d.star_nb, d.star_cell, d.star_edge, d.star_he, t->w.xbuf,
                     t->w.cap, t->w.cell_aux, t->w.partials, t->w.partials2, t->w.mpart,
                     t->w.t1_list,
@@ -322,7 +328,8 @@ int relax_impl(vtx_tissue t, int mode, void *X, const vtx_params *p, const vtx_r
         res->status = h.status == VTX_E_NONFINITE ? VTX_NOT_CONVERGED : h.status;
     }
     if (h.t1_overflow == 1) return fail(VTX_E_CAPACITY, "T1 pass: too many pending re-checks");
-    if (h.t1_overflow == 2) return fail(VTX_E_CAPACITY, "T1 made a cell span two images");
+    if (h.t1_overflow == 2)
+        return fail(VTX_E_CAPACITY, "T1 pass: corner-row pool exhausted or a cell spans two images");
     if (h.status == VTX_E_NONFINITE) return fail(VTX_E_NONFINITE, "non-finite forces in relaxation");
     return VTX_OK;
 }
@@ -375,6 +382,13 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
     UP(d.he_edge, S.he_edge);
     UP(d.edge_he, S.edge_he);
     UP(d.row_ptr, S.row_ptr);
+    UP(d.row_cap, S.row_cap);
+    {
+        const std::vector<int32_t> pt{(int32_t)(n_he + kRowSlack * n_cell)};
+        UP(d.pool_top, pt);
+    }
+    d.pool_start = (int32_t)(n_he + kRowSlack * n_cell);
+    d.corner_cap = (int32_t)S.corner.size();
     UP(d.corner, S.corner);
     UP(d.corner_he, S.corner_he);
     UP(d.nsides, S.nsides);
@@ -456,6 +470,8 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he) {
     DevTissue &d = t->d;
     if ((rc = upload_into(d.he, hev)) || (rc = upload_into(d.he_edge, S.he_edge)) ||
         (rc = upload_into(d.edge_he, S.edge_he)) || (rc = upload_into(d.row_ptr, S.row_ptr)) ||
+        (rc = upload_into(d.row_cap, S.row_cap)) ||
+        (rc = upload_into(d.pool_top, std::vector<int32_t>{d.pool_start})) ||
         (rc = upload_into(d.corner, S.corner)) || (rc = upload_into(d.corner_he, S.corner_he)) ||
         (rc = upload_into(d.nsides, S.nsides)) || (rc = upload_into(d.cell_he, S.cell_he)) ||
         (rc = upload_into(d.star_nb, S.star_nb)) || (rc = upload_into(d.star_cell, S.star_cell)) ||
@@ -515,9 +531,11 @@ int vtx_t1(vtx_tissue t, int32_t mode, void *X, const vtx_params *p, double l_mi
     launch_t1(t->d, t->w, mode, X, raw(p), l_min, l_new, s);
     if ((rc = check_launch("vtx_t1"))) return rc;
     if ((rc = read_ctl(t, 1, s))) return rc;
-    const LoopCtl &h = t->w.ctl_host[1];
+    const LoopCtl h = t->w.ctl_host[1];
     if (n_swap) *n_swap = h.n_t1;
     if (n_stretch) *n_stretch = h.n_stretch;
+    LoopCtl z2{};  // the evaluation control block must never stay `done`
+    if ((rc = reset_ctl(t, 1, z2, s))) return rc;
     if (h.t1_overflow) return fail(VTX_E_CAPACITY, "T1 pass overflow (%d)", h.t1_overflow);
     return VTX_OK;
 }

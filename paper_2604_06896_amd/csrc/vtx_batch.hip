@@ -152,7 +152,7 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
                *Aq = G.cg + 6 * (int64_t)nv;
         // cell coefficients at X*
         for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
-            const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
+            const int rb = t.row_ptr[c], nn = t.nsides[c];
             PosT A, P;
             cell_geom<PosT, PosT>(
                 t, X, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
@@ -307,6 +307,7 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
         int cur = 0;
         int64_t iter = 0, count = 0, n_t1 = 0, n_st = 0;
         int status = VTX_NOT_CONVERGED, result_buf = 0;
+        int bad_t1 = 0;  // meaningful in thread 0
         double last_mf = 0.0;
         for (;;) {
             PosT *Xc = bufs[cur], *Xn = bufs[cur ^ 1];
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
             __syncthreads();
             // cell pass
             for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
-                const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
+                const int rb = t.row_ptr[c], nn = t.nsides[c];
                 PosT A, P;  // in the position precision, as in the grid kernels
                 cell_geom<PosT, PosT>(
                     t, Xc, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P,
@@ -333,15 +334,21 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
                     arr[i] = i < ncand ? t.he_edge[t.corner_he[B.t1_list[i]]] : INT_MAX;
                 __syncthreads();
                 block_bitonic(arr, np2);
-                if (threadIdx.x == 0) {
+                if (threadIdx.x < 64) {  // one wave runs the pass
                     T1Counts r = t1_sequential<PosT, M>(t, Xc, p, cap, arr, ncand, extra,
                                                         o.l_min, o.l_new);
-                    n_t1 += r.swaps;
-                    n_st += r.stretches;
-                    s_changed = r.changed;
+                    if (threadIdx.x == 0) {
+                        n_t1 += r.swaps;
+                        n_st += r.stretches;
+                        s_changed = r.relocated;
+                        if (r.overflow) bad_t1 = r.overflow;
+                    }
                 }
                 __syncthreads();
-                if (s_changed) rebuild_rows_block(t, scan);
+                if (s_changed) {
+                    const int bad = rebuild_rows_block(t, scan);
+                    if (threadIdx.x == 0 && bad) bad_t1 = 2;
+                }
                 __syncthreads();
             }
             // mean of the nudge gradient over the vertices
@@ -389,7 +396,11 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
                 ++iter;
                 last_mf = m;
                 int done = 0;
-                if (!(m <= 1.7976931348623157e308)) {
+                if (bad_t1) {
+                    done = 1;
+                    status = VTX_E_CAPACITY;
+                    result_buf = cur;
+                } else if (!(m <= 1.7976931348623157e308)) {
                     done = 1;
                     status = VTX_E_NONFINITE;
                     result_buf = cur;
@@ -421,7 +432,7 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
         double e = 0.0;
         const PosT *Xr = (const PosT *)B.X;
         for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
-            const int rb = t.row_ptr[c], nn = t.row_ptr[c + 1] - rb;
+            const int rb = t.row_ptr[c], nn = t.nsides[c];
             PosT A, P;
             cell_geom<PosT, PosT>(
                 t, Xr, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
@@ -533,11 +544,16 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (res[i].status == VTX_E_NONFINITE) {
             res[i].status = VTX_NOT_CONVERGED;
             return set_error(VTX_E_NONFINITE, "non-finite forces in a batched relaxation");
         }
+        if (res[i].status == VTX_E_CAPACITY) {
+            res[i].status = VTX_NOT_CONVERGED;
+            return set_error(VTX_E_CAPACITY, "T1 pass overflow in a batched relaxation");
+        }
+    }
     return VTX_OK;
 }
 

@@ -195,13 +195,6 @@ __device__ __forceinline__ void cell_walk(const DevTissue &t, const PosT *X, int
     P = per;
 }
 
-template <typename PosT>
-__device__ __forceinline__ double cell_energy(const DevParams<PosT> &p, int c, double A,
-                                              double P) {
-    const double da = A - (double)p.a0(c), dp = P - (double)p.p0(c);
-    return (double)p.ka(c) * da * da + (double)p.kp(c) * dp * dp;
-}
-
 __device__ __forceinline__ void star_refresh(const DevTissue &t, int v, int h0) {
     const int nv = t.n_vert;
     int h = h0;
@@ -216,23 +209,108 @@ __device__ __forceinline__ void star_refresh(const DevTissue &t, int v, int h0) 
     }
 }
 
-// Cell-term coefficients of one cell recomputed exactly after a T1 step.
+// ------------------------------------------------------------------- T1
+// One half-edge record loaded as two 16-byte vectors.
+struct HeRec {
+    int prev, next, twin, src, tgt, face, ox, oy;
+};
+__device__ __forceinline__ HeRec he_rec(const DevTissue &t, int h) {
+    const int4 *r = reinterpret_cast<const int4 *>(t.he + 8 * (int64_t)h);
+    const int4 a = r[0], b = r[1];
+    return HeRec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+// Area and perimeter (FP64) of cell c read from its corner row, with the
+// two vertices of the edge under test at overridden positions and one
+// optional edit of the corner sequence:
+//   edit 1: drop vertex va;
+//   edit 2: put vertex vb, at the image of va plus (sx, sy), right before va.
+// Coordinates are unwrapped x + W L; the first corner is the origin.  The
+// first kRowPre corners and their positions are loaded before any is used.
+constexpr int kRowPre = 12;
+template <typename PosT>
+__device__ __noinline__ void row_geom(const DevTissue &t, const PosT *X, int c,
+                                         const PosOverride<PosT> &ov, int edit, int va, int vb,
+                                         int sx, int sy, double &A, double &P) {
+    const int rb = t.row_ptr[c], n = t.nsides[c];
+    int32_t w[kRowPre];
+    double qx[kRowPre], qy[kRowPre];
+#pragma unroll
+    for (int k = 0; k < kRowPre; ++k) w[k] = t.corner[rb + (k < n ? k : 0)];
+#pragma unroll
+    for (int k = 0; k < kRowPre; ++k) ov.get(X, id_of(w[k]), qx[k], qy[k]);
+    double x0 = 0.0, y0 = 0.0, px = 0.0, py = 0.0, a = 0.0, per = 0.0;
+    bool first = true;
+    auto emit = [&](double x, double y, int wx, int wy) {
+        const double rx = x + wx * t.Lx, ry = y + wy * t.Ly;
+        if (first) {
+            x0 = rx;
+            y0 = ry;
+            first = false;
+            return;
+        }
+        const double ux = rx - x0, uy = ry - y0;
+        const double dx = ux - px, dy = uy - py;
+        a += px * uy - py * ux;
+        per += sqrt(dx * dx + dy * dy);
+        px = ux;
+        py = uy;
+    };
+    auto corner = [&](int32_t wk, double x, double y) {
+        const int v = id_of(wk);
+        if (edit == 2 && v == va) {
+            double bx, by;
+            ov.get(X, vb, bx, by);
+            emit(bx, by, ox_of(wk) + sx, oy_of(wk) + sy);
+        }
+        if (edit == 1 && v == va) return;
+        emit(x, y, ox_of(wk), oy_of(wk));
+    };
+#pragma unroll
+    for (int k = 0; k < kRowPre; ++k)
+        if (k < n) corner(w[k], qx[k], qy[k]);
+    for (int k = kRowPre; k < n; ++k) {
+        const int32_t wk = t.corner[rb + k];
+        double x, y;
+        ov.get(X, id_of(wk), x, y);
+        corner(wk, x, y);
+    }
+    const double dx = -px, dy = -py;  // closing edge back to the first corner
+    per += sqrt(dx * dx + dy * dy);
+    A = 0.5 * a;
+    P = per;
+}
+
+template <typename PosT>
+__device__ __forceinline__ double cell_energy(const DevParams<PosT> &p, int c, double A,
+                                              double P) {
+    const double da = A - (double)p.a0(c), dp = P - (double)p.p0(c);
+    return (double)p.ka(c) * da * da + (double)p.kp(c) * dp * dp;
+}
+
+// Cell-term coefficients of one cell recomputed (FP64) after a T1 step.
 template <typename PosT, typename M>
 __device__ __forceinline__ void cell_refresh_cap(const DevTissue &t, const PosT *X,
-                                                 const DevParams<PosT> &p, M *cap, int c,
-                                                 int h0) {
+                                                 const DevParams<PosT> &p, M *cap, int c) {
     PosOverride<PosT> none{-1, -1, 0, 0, 0, 0};
     double A, P;
-    cell_walk<PosT>(t, X, h0, none, A, P);
+    row_geom<PosT>(t, X, c, none, 0, -1, -1, 0, 0, A, P);
     cap[2 * (int64_t)c] = (M)(2.0 * (double)p.ka(c) * (A - (double)p.a0(c)));
     cap[2 * (int64_t)c + 1] = (M)(2.0 * (double)p.kp(c) * (P - (double)p.p0(c)));
 }
 
-// Half-edge records changed by one neighbour exchange, saved for undo.
-struct T1Save {
-    int32_t id[10];
-    int32_t rec[10][8];
-};
+// Length of the edge src -> tgt with image offset (ox, oy), overridden
+// positions allowed.
+template <typename PosT>
+__device__ __forceinline__ double ov_len(const DevTissue &t, const PosT *X,
+                                         const PosOverride<PosT> &ov, int s, int g, int ox,
+                                         int oy) {
+    double xs, ys, xg, yg;
+    ov.get(X, s, xs, ys);
+    ov.get(X, g, xg, yg);
+    const double dx = xg + ox * t.Lx - xs, dy = yg + oy * t.Ly - ys;
+    return sqrt(dx * dx + dy * dy);
+}
 
 // Neighbour exchange of the edge of half-edge h (i -> j in C1, its twin
 // j -> i in C2; C3 is the third cell at i, C4 the third cell at j).
@@ -240,7 +318,7 @@ struct T1Save {
 // in C1) moves from j to i and the edge to b (next of the twin in C2) from
 // i to j; the moved half-edges change image offset by the offset of h so
 // that every edge vector is kept.
-__device__ __forceinline__ void t1_patch(const DevTissue &t, int h, T1Save *save) {
+__device__ __forceinline__ void t1_patch(const DevTissue &t, int h) {
     int32_t *he = t.he;
     auto R = [&](int x) { return he + 8 * (int64_t)x; };
     const int tw = R(h)[HT];
@@ -250,13 +328,6 @@ __device__ __forceinline__ void t1_patch(const DevTissue &t, int h, T1Save *save
     const int tp1 = R(p1)[HT], tn1 = R(n1)[HT];
     const int tp2 = R(p2)[HT], tn2 = R(n2)[HT];
     const int C3 = R(tp1)[HF], C4 = R(tn1)[HF];
-    if (save) {
-        const int ids[10] = {h, tw, p1, n1, p2, n2, tp1, tn1, tp2, tn2};
-        for (int a = 0; a < 10; ++a) {
-            save->id[a] = ids[a];
-            for (int b = 0; b < 8; ++b) save->rec[a][b] = R(ids[a])[b];
-        }
-    }
     const int hox = R(h)[HOX], hoy = R(h)[HOY];
     // C1: a->i -> i->c
     R(p1)[HN] = n1;
@@ -290,161 +361,242 @@ __device__ __forceinline__ void t1_patch(const DevTissue &t, int h, T1Save *save
     R(tw)[HF] = C3;
 }
 
-__device__ __forceinline__ void t1_restore(const DevTissue &t, const T1Save &s) {
-    for (int a = 0; a < 10; ++a)
-        for (int b = 0; b < 8; ++b) t.he[8 * (int64_t)s.id[a] + b] = s.rec[a][b];
-}
-
-__device__ __forceinline__ int face_sides(const DevTissue &t, int h0) {
-    int n = 0, h = h0;
-    do {
-        ++n;
-        h = t.he[8 * (int64_t)h + HN];
-    } while (h != h0 && n < 4096);
-    return n;
+// In-place edit of cell c's corner row after an exchange.
+//   edit 1: drop vertex va; the corner before it now leaves by half-edge nh.
+//   edit 2: insert vertex vb, leaving by half-edge nh, right before va, at
+//           the image of va plus (sx, sy).
+// Images are re-based so that the first corner has image 0.  A row without
+// a spare slot is first moved to the free pool at the end of the corner
+// arrays (*relocated is set; rows are compacted again after the pass).
+// Returns false on an inconsistency or when the pool is exhausted.
+__device__ __forceinline__ bool row_edit(const DevTissue &t, int c, int edit, int va, int vb,
+                                         int nh, int sx, int sy, int *relocated) {
+    int rb = t.row_ptr[c];
+    const int n = t.nsides[c];
+    if (edit == 2 && n + 1 > t.row_cap[c]) {
+        const int nb = *t.pool_top;
+        const int cap = n + 1 + kRowExtra;
+        if (nb + cap > t.corner_cap) return false;
+        for (int q = 0; q < n; ++q) {
+            t.corner[nb + q] = t.corner[rb + q];
+            t.corner_he[nb + q] = t.corner_he[rb + q];
+        }
+        *t.pool_top = nb + cap;
+        t.row_ptr[c] = nb;
+        t.row_cap[c] = cap;
+        rb = nb;
+        *relocated = 1;
+    }
+    int32_t *cw = t.corner + rb;
+    int32_t *ch = t.corner_he + rb;
+    int k = 0;
+    while (k < n && id_of(cw[k]) != va) ++k;
+    if (k == n) return false;
+    if (edit == 1) {
+        const int kp = (k + n - 1) % n;
+        ch[kp] = nh;
+        for (int q = k; q + 1 < n; ++q) {
+            cw[q] = cw[q + 1];
+            ch[q] = ch[q + 1];
+        }
+        t.nsides[c] = n - 1;
+    } else {
+        for (int q = n; q > k; --q) {
+            cw[q] = cw[q - 1];
+            ch[q] = ch[q - 1];
+        }
+        cw[k] = pack_id(vb, ox_of(cw[k + 1]) + sx, oy_of(cw[k + 1]) + sy);
+        ch[k] = nh;
+        t.nsides[c] = n + 1;
+    }
+    const int m = t.nsides[c];
+    const int bx = ox_of(cw[0]), by = oy_of(cw[0]);
+    if (bx || by)
+        for (int q = 0; q < m; ++q) cw[q] = pack_id(id_of(cw[q]), ox_of(cw[q]) - bx, oy_of(cw[q]) - by);
+    for (int q = 0; q < m; ++q)
+        if (ox_of(cw[q]) < -1 || ox_of(cw[q]) > 1 || oy_of(cw[q]) < -1 || oy_of(cw[q]) > 1)
+            return false;
+    return true;
 }
 
 // Result of one sequential T1 pass.
 struct T1Counts {
     int64_t swaps, stretches;
-    int changed;
-    int overflow;
+    int changed;    // topology changed
+    int relocated;  // a row moved to the pool: compact all rows after the pass
+    int overflow;   // 1: too many pending re-checks; 2: row edit failed
 };
 
-// Insert edge e into the small pending set `extra` (unsorted) if absent.
-__device__ __forceinline__ bool extra_insert(int32_t *extra, int &n_extra, int e) {
-    for (int a = 0; a < n_extra; ++a)
-        if (extra[a] == e) return true;
-    if (n_extra >= kT1Extra) return false;
-    extra[n_extra++] = e;
-    return true;
-}
-
 // Sequential T1 pass over the ascending candidate list `list[0..n)` (edge
-// ids, sorted, may hold duplicates and INT_MAX padding), run by ONE thread.
-// Each candidate is re-checked with the current positions; edges next to a
-// processed edge that become short are visited in turn as well, so the
-// result equals visiting every edge in ascending id order.
+// ids, sorted, may hold duplicates and INT_MAX padding), run by the 64
+// lanes of ONE wave with wave-uniform control flow.  Each candidate is
+// re-checked with the current positions; edges next to a processed edge
+// that become short are visited in turn as well, so the result equals
+// visiting every edge in ascending id order.  Both candidates are evaluated
+// on the four cells around the edge (lanes 0-7: stretch on cells C1..C4,
+// exchange on C1..C4, read from their corner rows with the exchange applied
+// as row edits) and the five edges at its ends; everything else is common
+// to both.  Lane 0 writes the result; the kept candidate's cell geometry
+// gives the new cell coefficients.  Not inlined: it must not raise the
+// register pressure of the loops around it.
 template <typename PosT, typename M>
-__device__ T1Counts t1_sequential(const DevTissue &t, PosT *X, const DevParams<PosT> &p,
-                                  M *cap, const int32_t *list, int n, int32_t *extra,
-                                  double l_min, double l_new) {
-    T1Counts out{0, 0, 0, 0};
+__device__ __noinline__ T1Counts t1_sequential(const DevTissue &t, PosT *X, const DevParams<PosT> &p,
+                                               M *cap, const int32_t *list, int n, int32_t *extra,
+                                               double l_min, double l_new) {
+    const int lane = threadIdx.x & 63;
+    T1Counts out{0, 0, 0, 0, 0};
     int pos = 0, n_extra = 0;
     int last = -1;
     const double hl = 0.5 * l_new;
     for (;;) {
-        // next edge: min of list[pos] and the pending set
-        int e = 0x7fffffff, ea = -1;
+        // next edge: min of list[pos] and the pending set.  Every lane keeps
+        // the same bookkeeping (the LDS set is written by all lanes with the
+        // same values), so no lane depends on another's writes.
+        int e = 0x7fffffff;
         while (pos < n && list[pos] <= last) ++pos;
         if (pos < n) e = list[pos];
         for (int a = 0; a < n_extra; ++a)
-            if (extra[a] <= last) {
-                extra[a] = extra[--n_extra];
-                --a;
-            }
-        for (int a = 0; a < n_extra; ++a)
-            if (extra[a] < e) { e = extra[a]; ea = a; }
+            if (extra[a] < e) e = extra[a];
         if (e == 0x7fffffff) break;
-        if (ea >= 0) extra[ea] = extra[--n_extra];
-        else ++pos;
+        if (pos < n && list[pos] == e) ++pos;
+        {   // drop e (and anything below it) from the pending set
+            int m = 0;
+            for (int a = 0; a < n_extra; ++a) {
+                const int v = extra[a];
+                if (v > e) extra[m++] = v;
+            }
+            n_extra = m;
+        }
         last = e;
 
         const int h = t.edge_he[e];
-        const int32_t *rh = t.he + 8 * (int64_t)h;
-        const int i = rh[HS], j = rh[HG];
-        const int ohx = rh[HOX], ohy = rh[HOY];
+        const HeRec rh = he_rec(t, h);
+        const int i = rh.src, j = rh.tgt;
         const double xi = (double)X[2 * (int64_t)i], yi = (double)X[2 * (int64_t)i + 1];
         const double xj = (double)X[2 * (int64_t)j], yj = (double)X[2 * (int64_t)j + 1];
-        const double dx = pdiff<double>(xj, xi, ohx, t.Lx), dy = pdiff<double>(yj, yi, ohy, t.Ly);
+        const double dx = pdiff<double>(xj, xi, rh.ox, t.Lx), dy = pdiff<double>(yj, yi, rh.oy, t.Ly);
         const double l = sqrt(dx * dx + dy * dy);
         if (!(l < l_min)) continue;
         double ux = 1.0, uy = 0.0;
         if (l > 0.0) { ux = dx / l; uy = dy / l; }
         const double mx = xi + 0.5 * dx, my = yi + 0.5 * dy;
-        const double sx = ohx * t.Lx, sy = ohy * t.Ly;
-        PosOverride<PosT> S{i, j, mx - hl * ux, my - hl * uy, mx + hl * ux - sx, my + hl * uy - sy};
+        const double sxL = rh.ox * t.Lx, syL = rh.oy * t.Ly;
+        const PosOverride<PosT> S{i, j, mx - hl * ux, my - hl * uy, mx + hl * ux - sxL, my + hl * uy - syL};
         const double nx = -uy, ny = ux;
-        PosOverride<PosT> T{i, j, mx + hl * nx, my + hl * ny, mx - hl * nx - sx, my - hl * ny - sy};
+        const PosOverride<PosT> T{i, j, mx + hl * nx, my + hl * ny, mx - hl * nx - sxL, my - hl * ny - syL};
 
-        const int tw = rh[HT];
-        const int p1 = rh[HP], n1 = rh[HN];
-        const int p2 = t.he[8 * (int64_t)tw + HP], n2 = t.he[8 * (int64_t)tw + HN];
-        const int tp1 = t.he[8 * (int64_t)p1 + HT], tn1 = t.he[8 * (int64_t)n1 + HT];
-        const int tp2 = t.he[8 * (int64_t)p2 + HT];
-        const int C1 = rh[HF], C2 = t.he[8 * (int64_t)tw + HF];
-        const int C3 = t.he[8 * (int64_t)tp1 + HF], C4 = t.he[8 * (int64_t)tn1 + HF];
+        const int tw = rh.twin, p1 = rh.prev, n1 = rh.next;
+        const HeRec rt = he_rec(t, tw), rp1 = he_rec(t, p1), rn1 = he_rec(t, n1);
+        const int p2 = rt.prev, n2 = rt.next;
+        const HeRec rp2 = he_rec(t, p2), rn2 = he_rec(t, n2);
+        const int tp1 = rp1.twin, tn1 = rn1.twin, tn2 = rn2.twin;
+        const int C1 = rh.face, C2 = rt.face;
+        const int C3 = he_rec(t, tp1).face, C4 = he_rec(t, tn1).face;
         const bool distinct = C1 != C2 && C1 != C3 && C1 != C4 && C2 != C3 && C2 != C4 && C3 != C4;
+        const bool admissible = distinct && t.nsides[C1] > 3 && t.nsides[C2] > 3;
+
+        // lanes 0..3: stretch geometry of C1..C4; lanes 4..7: exchange geometry
+        const int q = lane & 3;
+        const int cq = q == 0 ? C1 : q == 1 ? C2 : q == 2 ? C3 : C4;
+        double A = 0.0, P = 0.0, Eq = 0.0;
+        if (lane < 4 || (lane < 8 && admissible)) {
+            if (lane < 4) {
+                row_geom<PosT>(t, X, cq, S, 0, -1, -1, 0, 0, A, P);
+            } else {
+                // exchange: C1 drops j, C2 drops i, C3 gains j before i,
+                // C4 gains i before j
+                const int ed = q < 2 ? 1 : 2;
+                const int va = (q == 0 || q == 3) ? j : i;
+                const int vb = q == 2 ? j : (q == 3 ? i : -1);
+                const int sx = q == 2 ? rh.ox : (q == 3 ? -rh.ox : 0);
+                const int sy = q == 2 ? rh.oy : (q == 3 ? -rh.oy : 0);
+                row_geom<PosT>(t, X, cq, T, ed, va, vb, sx, sy, A, P);
+            }
+            Eq = cell_energy<PosT>(p, cq, A, P);
+        }
         bool take_T = false;
-        if (distinct && t.nsides[C1] > 3 && t.nsides[C2] > 3) {
-            // local energies: the four cells around the edge and the five
-            // edges ending at i or j (everything else is unchanged)
-            const int cells[4] = {C1, C2, C3, C4};
-            const int walk[4] = {p1, p2, tp1, tp2};  // half-edges in these cells before and after
-            const int edges[5] = {h, p1, n1, p2, n2};
-            double ES = 0.0, ET = 0.0;
-            for (int a = 0; a < 4; ++a) {
-                double A, P;
-                cell_walk<PosT>(t, X, walk[a], S, A, P);
-                ES += cell_energy<PosT>(p, cells[a], A, P);
-            }
-            for (int a = 0; a < 5; ++a) {
-                double ex, ey;
-                he_vec<PosT>(t, X, edges[a], S, ex, ey);
-                ES += (double)p.lm(t.he_edge[edges[a]]) * sqrt(ex * ex + ey * ey);
-            }
-            T1Save sv;
-            t1_patch(t, h, &sv);
-            for (int a = 0; a < 4; ++a) {
-                double A, P;
-                cell_walk<PosT>(t, X, walk[a], T, A, P);
-                ET += cell_energy<PosT>(p, cells[a], A, P);
-            }
-            for (int a = 0; a < 5; ++a) {
-                double ex, ey;
-                he_vec<PosT>(t, X, edges[a], T, ex, ey);
-                ET += (double)p.lm(t.he_edge[edges[a]]) * sqrt(ex * ex + ey * ey);
-            }
-            take_T = ET < ES;
-            if (!take_T) t1_restore(t, sv);
+        if (admissible) {
+            const double ES = ((__shfl(Eq, 0, 64) + __shfl(Eq, 1, 64)) + __shfl(Eq, 2, 64)) +
+                              __shfl(Eq, 3, 64);
+            const double ET0 = ((__shfl(Eq, 4, 64) + __shfl(Eq, 5, 64)) + __shfl(Eq, 6, 64)) +
+                               __shfl(Eq, 7, 64);
+            // edges i->c and j->b replace j->c and i->b in the exchange
+            const double lh = (double)p.lm(e);
+            const double lp1 = (double)p.lm(t.he_edge[p1]), ln1 = (double)p.lm(t.he_edge[n1]);
+            const double lp2 = (double)p.lm(t.he_edge[p2]), ln2 = (double)p.lm(t.he_edge[n2]);
+            const double ESe = lh * ov_len<PosT>(t, X, S, i, j, rh.ox, rh.oy) +
+                               lp1 * ov_len<PosT>(t, X, S, rp1.src, i, rp1.ox, rp1.oy) +
+                               ln1 * ov_len<PosT>(t, X, S, j, rn1.tgt, rn1.ox, rn1.oy) +
+                               lp2 * ov_len<PosT>(t, X, S, rp2.src, j, rp2.ox, rp2.oy) +
+                               ln2 * ov_len<PosT>(t, X, S, i, rn2.tgt, rn2.ox, rn2.oy);
+            const double ETe = lh * ov_len<PosT>(t, X, T, i, j, rh.ox, rh.oy) +
+                               lp1 * ov_len<PosT>(t, X, T, rp1.src, i, rp1.ox, rp1.oy) +
+                               ln1 * ov_len<PosT>(t, X, T, i, rn1.tgt, rn1.ox + rh.ox, rn1.oy + rh.oy) +
+                               lp2 * ov_len<PosT>(t, X, T, rp2.src, j, rp2.ox, rp2.oy) +
+                               ln2 * ov_len<PosT>(t, X, T, j, rn2.tgt, rn2.ox - rh.ox, rn2.oy - rh.oy);
+            take_T = ET0 + ETe < ES + ESe;
         }
         const PosOverride<PosT> &W = take_T ? T : S;
-        X[2 * (int64_t)i] = (PosT)W.xi;
-        X[2 * (int64_t)i + 1] = (PosT)W.yi;
-        X[2 * (int64_t)j] = (PosT)W.xj;
-        X[2 * (int64_t)j + 1] = (PosT)W.yj;
+        // the kept candidate's lanes write the new coefficients of C1..C4
+        if ((take_T && lane >= 4 && lane < 8) || (!take_T && lane < 4)) {
+            cap[2 * (int64_t)cq] = (M)(2.0 * (double)p.ka(cq) * (A - (double)p.a0(cq)));
+            cap[2 * (int64_t)cq + 1] = (M)(2.0 * (double)p.kp(cq) * (P - (double)p.p0(cq)));
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            X[2 * (int64_t)i] = (PosT)W.xi;
+            X[2 * (int64_t)i + 1] = (PosT)W.yi;
+            X[2 * (int64_t)j] = (PosT)W.xj;
+            X[2 * (int64_t)j + 1] = (PosT)W.yj;
+            if (take_T) {
+                t1_patch(t, h);
+                if (t.cell_he[C1] == h) t.cell_he[C1] = n1;
+                if (t.cell_he[C2] == tw) t.cell_he[C2] = n2;
+                // rows: C1 drops j (i now leaves by n1), C2 drops i (j leaves
+                // by n2), C3 gains j (leaving by tw) before i, C4 gains i (by
+                // h) before j
+                bool ok = row_edit(t, C1, 1, j, -1, n1, 0, 0, &out.relocated);
+                ok = row_edit(t, C2, 1, i, -1, n2, 0, 0, &out.relocated) && ok;
+                ok = row_edit(t, C3, 2, i, j, tw, rh.ox, rh.oy, &out.relocated) && ok;
+                ok = row_edit(t, C4, 2, j, i, h, -rh.ox, -rh.oy, &out.relocated) && ok;
+                if (!ok) out.overflow = 2;
+                // stars of i and j are rebuilt; c and b changed neighbour
+                star_refresh(t, i, h);
+                star_refresh(t, j, tw);
+                star_refresh(t, rn1.tgt, tn1);   // c
+                star_refresh(t, rn2.tgt, tn2);   // b
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        out.overflow = __shfl(out.overflow, 0, 64);
+        out.relocated = __shfl(out.relocated, 0, 64);
+        if (out.overflow == 2) return out;
         if (take_T) {
             ++out.swaps;
             out.changed = 1;
-            t.nsides[C1] -= 1;
-            t.nsides[C2] -= 1;
-            t.nsides[C3] += 1;
-            t.nsides[C4] += 1;
-            if (t.cell_he[C1] == h) t.cell_he[C1] = n1;
-            if (t.cell_he[C2] == tw) t.cell_he[C2] = n2;
-            // stars of i and j are rebuilt; c and b changed neighbour
-            star_refresh(t, i, h);
-            star_refresh(t, j, tw);
-            star_refresh(t, t.he[8 * (int64_t)n1 + HG], tn1);   // c
-            star_refresh(t, t.he[8 * (int64_t)n2 + HG], t.he[8 * (int64_t)n2 + HT]);  // b
         } else {
             ++out.stretches;
         }
-        // cell terms of the four cells around the edge, exactly
-        cell_refresh_cap<PosT, M>(t, X, p, cap, C1, p1);
-        cell_refresh_cap<PosT, M>(t, X, p, cap, C2, p2);
-        cell_refresh_cap<PosT, M>(t, X, p, cap, C3, tp1);
-        cell_refresh_cap<PosT, M>(t, X, p, cap, C4, tp2);
-        // the four other edges at i and j may have become short
+        // the four other edges at i and j may have become short: a->i, and
+        // i->c, d->j, j->b after an exchange (j->c, i->b after a stretch)
         const int nbr[4] = {p1, n1, p2, n2};
+        const int ns[4] = {rp1.src, take_T ? i : j, rp2.src, take_T ? j : i};
+        const int ng[4] = {i, rn1.tgt, j, rn2.tgt};
+        const int nox[4] = {rp1.ox, rn1.ox + (take_T ? rh.ox : 0), rp2.ox, rn2.ox - (take_T ? rh.ox : 0)};
+        const int noy[4] = {rp1.oy, rn1.oy + (take_T ? rh.oy : 0), rp2.oy, rn2.oy - (take_T ? rh.oy : 0)};
         for (int a = 0; a < 4; ++a) {
             const int e2 = t.he_edge[nbr[a]];
             if (e2 <= e) continue;
-            PosOverride<PosT> none{-1, -1, 0, 0, 0, 0};
-            double ex, ey;
-            he_vec<PosT>(t, X, nbr[a], none, ex, ey);
-            if (sqrt(ex * ex + ey * ey) < l_min)
-                if (!extra_insert(extra, n_extra, e2)) out.overflow = 1;
+            if (ov_len<PosT>(t, X, W, ns[a], ng[a], nox[a], noy[a]) < l_min) {
+                bool present = false;
+                for (int b = 0; b < n_extra; ++b) present |= extra[b] == e2;
+                if (!present) {
+                    if (n_extra >= kT1Extra) out.overflow = 1;
+                    else extra[n_extra++] = e2;
+                }
+            }
         }
     }
     return out;
@@ -481,7 +633,7 @@ __device__ __forceinline__ int rebuild_rows_block(const DevTissue &t, int32_t *s
     const int nc = t.n_cell;
     for (int base = 0; base < nc; base += blockDim.x) {
         const int c = base + threadIdx.x;
-        const int v = c < nc ? t.nsides[c] : 0;
+        const int v = c < nc ? t.nsides[c] + kRowSlack : 0;
         sh_scan[threadIdx.x] = v;
         __syncthreads();
         for (int off = 1; off < (int)blockDim.x; off <<= 1) {
@@ -495,11 +647,16 @@ __device__ __forceinline__ int rebuild_rows_block(const DevTissue &t, int32_t *s
         if (threadIdx.x == blockDim.x - 1) carry += sh_scan[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x == 0) t.row_ptr[nc] = carry;
+    if (threadIdx.x == 0) {
+        t.row_ptr[nc] = carry;
+        *t.pool_top = t.pool_start;
+        if (carry > t.pool_start) bad = 1;
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const int h0 = t.cell_he[c];
         int base = t.row_ptr[c];
+        t.row_cap[c] = t.nsides[c] + kRowSlack;
         int wx = 0, wy = 0, h = h0, k = 0;
         do {
             const int32_t *r = t.he + 8 * (int64_t)h;
@@ -529,7 +686,7 @@ __device__ __forceinline__ void hvp_cell_one(const DevTissue &t, const PosT *__r
                                              int c) {
     using C = PosT;
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
-    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    const int rb = t.row_ptr[c], n = t.nsides[c];
     const int32_t w0 = t.corner[rb];
     const auto p0 = ld2(X, id_of(w0));
     auto rel = [&](int k, C &rx, C &ry, C &vx, C &vy) {
@@ -636,7 +793,7 @@ template <typename PosT>
 __device__ __forceinline__ double contract_p0_one(const DevTissue &t, const PosT *X,
                                                   const DevParams<PosT> &p, const double *mu,
                                                   int c) {
-    const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+    const int rb = t.row_ptr[c], n = t.nsides[c];
     double dP = 0.0;
     for (int k = 0; k < n; ++k) {
         const int h = t.corner_he[rb + k];

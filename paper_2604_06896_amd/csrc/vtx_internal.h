@@ -17,6 +17,8 @@ constexpr int kBlock = 256;          // threads per block of the grid kernels
 constexpr int kRowLds = 16 * kBlock; // corner ints staged in LDS per cell block
 constexpr int kT1SortCap = 4096;     // T1 candidates sorted in LDS
 constexpr int kT1Extra = 256;        // pending re-checks during one T1 pass
+constexpr int kRowSlack = 2;         // spare slots per row after a compaction
+constexpr int kRowExtra = 4;         // spare slots of a row moved to the pool
 
 __host__ __device__ inline int32_t pack_id(int32_t id, int ox, int oy) {
     return (int32_t)((uint32_t)id | ((uint32_t)((ox + 1) | ((oy + 1) << 2)) << kIdBits));
@@ -36,7 +38,11 @@ struct DevTissue {
     int32_t *he;         // [n_he][8] current topology
     int32_t *he_edge;    // [n_he] edge id of each half-edge
     int32_t *edge_he;    // [n_edge] lower half-edge of each edge
-    int32_t *row_ptr;    // [n_cell + 1] cell -> corner rows
+    int32_t *row_ptr;    // [n_cell + 1] start of each cell's corner row
+    int32_t *row_cap;    // [n_cell] slots of each row (nsides[c] corners + spare)
+    int32_t *pool_top;   // device int: next free slot of the relocation pool
+    int32_t pool_start;  // first slot of the pool (rows above it are relocated)
+    int32_t corner_cap;  // slots in corner / corner_he
     int32_t *corner;     // [n_he] packed vertex id + image relative to corner 0
     int32_t *corner_he;  // [n_he] half-edge leaving each corner
     int32_t *nsides;     // [n_cell]

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
     const bool det = (flags & F_T1DET) != 0;
     double e = 0.0;
     if (c < nc) {
-        const int rb = t.row_ptr[c], n = t.row_ptr[c + 1] - rb;
+        const int rb = t.row_ptr[c], n = t.nsides[c];
         // Area and perimeter in the precision of the positions: the
         // coefficients cA, cP come from differences (A - A0, P - P0) that
         // cancel, and in FP32 their rounding (~1e-6 on an edge tension) would
@@ -305,19 +305,25 @@ __global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<P
         arr[i] = i < n ? t.he_edge[t.corner_he[list_g[i]]] : INT_MAX;
     __syncthreads();
     block_bitonic(arr, np2);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // one wave runs the pass
         T1Counts r = t1_sequential<PosT, M>(t, X, p, cap, arr, n, extra, l_min, l_new);
+        if (threadIdx.x == 0) {
         ctl->n_t1 += r.swaps;
         ctl->n_stretch += r.stretches;
-        if (r.overflow) ctl->t1_overflow = 1;
+        if (r.overflow) ctl->t1_overflow = r.overflow;
         ctl->t1_count = 0;
-        s_changed = r.changed;
+        s_changed = r.relocated;
         if (r.changed) ctl->topo_changed = 1;
+        if (r.overflow == 2) ctl->done = 1;  // stop the loop; the host reports it
+        }
     }
     __syncthreads();
-    if (s_changed) {
+    if (s_changed) {  // rows moved to the pool: compact them again
         const int bad = rebuild_rows_block(t, scan);
-        if (threadIdx.x == 0 && bad) ctl->t1_overflow = 2;
+        if (threadIdx.x == 0 && bad) {
+            ctl->t1_overflow = 2;
+            ctl->done = 1;
+        }
     }
 }
 
