@@ -14,7 +14,6 @@ namespace vtx {
 constexpr int kIdBits = 28;
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
 constexpr int kBlock = 256;          // threads per block of the grid kernels
-constexpr int kRowLds = 16 * kBlock; // corner ints staged in LDS per cell block
 constexpr int kT1SortCap = 4096;     // T1 candidates sorted in LDS
 constexpr int kT1Extra = 256;        // pending re-checks during one T1 pass
 constexpr int kRowSlack = 2;         // spare slots per row after a compaction
@@ -92,7 +91,7 @@ struct Workspace {
     double *cell_aux;    // per-cell auxiliaries (HVP: dA, dP), double [n_cell][2]
     double *partials;    // per-block partial sums (double)
     double *partials2;
-    double *mpart;       // per-block max |F| partials
+    double *mpart;       // per-block (energy, max |F|) partials, double2
     int32_t *t1_list;    // [n_edge] candidate corner indices
     LoopCtl *ctl;        // device control block
     LoopCtl *ctl_host;   // pinned host mirror
@@ -146,9 +145,55 @@ __device__ __forceinline__ void st2(T *p, int64_t i, T x, T y) {
     reinterpret_cast<typename Vec2<T>::type *>(p)[i] = v;
 }
 
+// ------------------------------------------------------------ reductions
+// Wave-wide reductions of a double with DPP lane moves (no LDS traffic):
+// pairs of lanes (xor 1, xor 2 in each quad), then the two quads of each
+// 8-lane half-row (half-row mirror), then the two halves of each 16-lane
+// row (row mirror); every lane then holds its row's total, and the four
+// row totals are read with readlane.  The order of operations is fixed, so
+// the result is deterministic, and it is the same in every lane.  All 64
+// lanes must be active.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, Ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), Ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7-i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15-i within 16
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+// Max that keeps NaN visible (fmax drops a NaN operand).
+__device__ __forceinline__ double nanmax(double a, double b) {
+    return (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(a, b);
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = nanmax(v, dpp_f64<kDppXor1>(v));
+    v = nanmax(v, dpp_f64<kDppXor2>(v));
+    v = nanmax(v, dpp_f64<kDppHalfMirror>(v));
+    v = nanmax(v, dpp_f64<kDppMirror>(v));
+    return nanmax(nanmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+                  nanmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // Block-wide sum of a double (fixed order: deterministic for a fixed block size).
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    v = wave_sum(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sh[wid] = v;
@@ -162,7 +207,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 }
 
 __device__ __forceinline__ double block_max(double v, double *sh) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    v = wave_max(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sh[wid] = v;
@@ -170,7 +215,29 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     double r = 0.0;
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
-        for (int w = 0; w < nw; ++w) r = fmax(r, sh[w]);
+        for (int w = 0; w < nw; ++w) r = nanmax(r, sh[w]);
+    }
+    return r;
+}
+
+// Sum of `s` and max of `m` over the block with one barrier; `sh` holds
+// 2 doubles per wave and must not be in use by the block.  Valid in thread 0.
+__device__ __forceinline__ double2 block_sum_max(double s, double m, double *sh) {
+    s = wave_sum(s);
+    m = wave_max(m);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[2 * wid] = s;
+        sh[2 * wid + 1] = m;
+    }
+    __syncthreads();
+    double2 r{0.0, 0.0};
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) {
+            r.x += sh[2 * w];
+            r.y = nanmax(r.y, sh[2 * w + 1]);
+        }
     }
     return r;
 }
@@ -189,16 +256,19 @@ __device__ __forceinline__ double block_sum_array(const double *part, int n, int
     return block_sum(s, sh);
 }
 
-// Called by thread 0 after the block's results are stored: returns true in
-// exactly one block (the last to arrive), which then sees every block's
-// stores.  The counter is reset by that block.
+// Called by thread 0 after the block's results are stored (and after a
+// barrier, so the block's other stores have reached the cache): returns
+// true in exactly one block (the last to arrive), which then sees every
+// block's stores.  Arrivals only release; the acquire is taken once, by the
+// last block.  On this multi-XCD part a device-scope release writes back the
+// XCD's L2 and an acquire invalidates it, so each costs tens of ns.  The
+// counter is reset by the last block.
 __device__ __forceinline__ bool last_block(unsigned int *counter) {
-    __threadfence();
-    unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-    bool last = prev == gridDim.x - 1;
+    const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    const bool last = prev == gridDim.x - 1;
     if (last) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return last;

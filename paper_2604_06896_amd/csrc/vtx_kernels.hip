@@ -2,13 +2,13 @@
 //
 // Hot path per energy/force evaluation (VertAX, arXiv 2604.06896, Methods,
 // "Vertex model formulation"):
-//   k_cell    one lane per cell: corner rows staged through LDS, shoelace
+//   k_cell    one lane per cell: corner row read directly, shoelace
 //             area and perimeter in a cell-local frame, cA = 2K_A(A-A0),
 //             cP = 2K_P(P-P0), FP64 energy partial per block;
 //   k_vertex  one lane per 3-valent vertex: gathers its 3 neighbours, 3 cells
 //             and 3 edge tensions and forms F with no atomics; the max |F|
-//             and energy are reduced per block and finished by the last block
-//             (fixed order, deterministic).  In relaxation it also takes the
+//             and energy are reduced per block and finished by the last
+//             block or by k_finish (fixed order, deterministic).  In relaxation it also takes the
 //             gradient-descent step and runs the convergence test on the
 //             device (Methods, "Simulation engine").
 //   k_t1      one workgroup: sequential T1 pass over the short edges flagged
@@ -34,17 +34,9 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
                                                  const PosT *__restrict__ Xt,
                                                  double *__restrict__ npart) {
     if (ctl->done) return;
-    __shared__ int32_t rows[kRowLds];
     __shared__ double sh[kBlock / 64];
     const int nc = t.n_cell;
-    const int c0 = xcd_block() * kBlock;
-    const int c = c0 + threadIdx.x;
-    const int cend = min(c0 + kBlock, nc);
-    const int base = t.row_ptr[c0], top = t.row_ptr[cend];
-    const bool staged = top - base <= kRowLds;
-    if (staged)
-        for (int i = threadIdx.x; i < top - base; i += kBlock) rows[i] = t.corner[base + i];
-    __syncthreads();
+    const int c = xcd_block() * kBlock + threadIdx.x;
     const bool det = (flags & F_T1DET) != 0;
     double e = 0.0;
     if (c < nc) {
@@ -53,15 +45,12 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
         // coefficients cA, cP come from differences (A - A0, P - P0) that
         // cancel, and in FP32 their rounding (~1e-6 on an edge tension) would
         // exceed a 1e-6 force tolerance.  The force gather stays in M.
+        // (Staging the block's rows through LDS first measured slower: the
+        // rows of consecutive cells are adjacent, so these reads share lines.)
         PosT A, P;
-        if (staged)
-            cell_geom<PosT, PosT>(
-                t, X, n, [&](int k) { return rows[rb - base + k]; }, rb, A, P, det,
-                (PosT)lmin2, t1_list, &ctl->t1_count);
-        else
-            cell_geom<PosT, PosT>(
-                t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, det, (PosT)lmin2,
-                t1_list, &ctl->t1_count);
+        cell_geom<PosT, PosT>(
+            t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, det, (PosT)lmin2,
+            t1_list, &ctl->t1_count);
         const PosT ka = p.ka(c), kp = p.kp(c);
         const PosT da = A - p.a0(c), dp = P - p.p0(c);
         st2(cap, c, (M)((PosT)2 * ka * da), (M)((PosT)2 * kp * dp));
@@ -101,17 +90,19 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
 }
 
 // ----------------------------------------------------------------- vertex
-// Grids up to this many blocks finish their reductions in the last block
-// to arrive; larger grids leave per-block partials to k_finish, because one
-// arrival atomic per block on a single address serialises (~25 ns each).
+// Each block stores its (energy, max |F|) partial.  Grids up to
+// kLastBlockMax blocks finish the reduction in the last block to arrive;
+// larger grids leave it to k_finish.  An arrival needs a device-scope
+// release and acquire, which on this multi-XCD part write back and
+// invalidate the XCD's L2 (tens of ns each, and they serialise): thousands
+// of arrivals cost far more than one extra launch.
 constexpr int kLastBlockMax = 128;
 
 struct VertexArgs {
     LoopCtl *ctl;
-    const double *epart_cell;
+    const double *epart_cell;  // per-block cell energies of the preceding k_cell
     int n_epart_cell;
-    double *epart_vert;
-    double *mpart;      // per-block max |F|
+    double2 *part;      // per-block (energy, max |F|)
     int finish;         // 1: the last block finishes here; 0: k_finish does
     double *E_out;
     double *maxf_out;
@@ -154,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__re
                                                    PosT *__restrict__ out, DevParams<PosT> p,
                                                    const M *__restrict__ cap, VertexArgs a) {
     if (MODE == 1 && a.ctl->done) return;
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[2 * (kBlock / 64)];
     const int v = xcd_block() * kBlock + threadIdx.x;
     double el = 0.0, mf = 0.0;
     if (v < t.n_vert) {
@@ -189,15 +180,16 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__re
             st2(out, v, (PosT)((double)xi + a.eta * gx), (PosT)((double)yi + a.eta * gy));
         }
     }
-    if (MODE == 0 && a.E_out) {
-        const double s = block_sum(el, sh);
-        if (threadIdx.x == 0) a.epart_vert[blockIdx.x] = s;
-    }
     if (MODE == 1 || a.maxf_out || a.E_out) {
-        const double m = block_max(mf, sh);
+        // block b also takes the cell-pass energy partials b, b + grid, ...
+        double ec = 0.0;
+        if (MODE == 0 && a.E_out && threadIdx.x == 0)
+            for (int j = blockIdx.x; j < a.n_epart_cell; j += gridDim.x) ec += a.epart_cell[j];
+        double2 r = block_sum_max(el, mf, sh);
         __shared__ int s_last;
         if (threadIdx.x == 0) {
-            a.mpart[blockIdx.x] = m;
+            r.x += ec;
+            a.part[blockIdx.x] = r;
             s_last = a.finish ? last_block(&a.ctl->arrive) : 0;
         }
         __syncthreads();
@@ -205,74 +197,47 @@ __global__ __launch_bounds__(kBlock) void k_vertex(DevTissue t, const PosT *__re
     }
 }
 
-// Per-thread sum of p[threadIdx.x + j * blockDim.x] in a fixed order, with
-// eight independent loads in flight per step (a plain `s += p[i]` loop waits
-// for each load before the next).
-__device__ __forceinline__ double strided_sum(const double *p, int n) {
-    double s = 0.0;
-    for (int base = 0; base < n; base += 8 * (int)blockDim.x) {
-        double x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
-            x[u] = i < n ? p[i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s += x[u];
-    }
-    return s;
-}
-
-// Fixed-order reductions of the per-block partials of one evaluation (or one
-// relaxation step), then the result / the convergence control.  `plain`:
-// the partials were written by an earlier kernel, so ordinary loads see them;
-// otherwise (last block of the same kernel) they are read at device scope.
+// Fixed-order reduction of the per-block (energy, max |F|) partials of one
+// evaluation (or one relaxation step), then the result / the convergence
+// control.  `plain`: the partials were written by an earlier kernel, so
+// ordinary loads see them; otherwise (last block of the same kernel) they
+// are read at device scope.  Each thread takes a fixed strided subset with
+// eight loads in flight, so the order does not depend on which block runs it.
 template <int MODE>
 __device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk, double *sh,
                                                   bool plain) {
-    double E = 0.0;
-    if (MODE == 0 && a.E_out) {
-        if (plain) {
-            const double ec = block_sum(strided_sum(a.epart_cell, a.n_epart_cell), sh);
-            E = ec + block_sum(strided_sum(a.epart_vert, nblk), sh);
-        } else {
-            const double ec = block_sum_array(a.epart_cell, a.n_epart_cell, 1, sh);
-            const double ev = block_sum_array(a.epart_vert, nblk, 1, sh);
-            E = ec + ev;
-        }
-    }
-    double m = 0.0;
-    bool nan = false;
-    if (plain) {
-        for (int base = 0; base < nblk; base += 8 * (int)blockDim.x) {
-            double x[8];
+    double e = 0.0, m = 0.0;
+    for (int base = 0; base < nblk; base += 8 * (int)blockDim.x) {
+        double2 x[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
-                x[u] = i < nblk ? a.mpart[i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                m = fmax(m, x[u]);
-                nan |= !(x[u] == x[u]);  // fmax drops NaN; keep it visible
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+            x[u] = double2{0.0, 0.0};
+            if (i < nblk) {
+                if (plain) {
+                    x[u] = a.part[i];
+                } else {
+                    const double *q = reinterpret_cast<const double *>(a.part + i);
+                    x[u].x = ld_acquire(q);
+                    x[u].y = ld_acquire(q + 1);
+                }
             }
         }
-    } else {
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-            const double x = __hip_atomic_load(a.mpart + i, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-            m = fmax(m, x);
-            nan |= !(x == x);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            e += x[u].x;
+            m = nanmax(m, x[u].y);
         }
     }
-    if (nan) m = INFINITY;
-    const double mfin = block_max(m, sh);
+    __syncthreads();  // `sh` may still be read by the block's own partial
+    const double2 r = block_sum_max(e, m, sh);
     if (threadIdx.x == 0) {
+        const double mfin = r.y != r.y ? INFINITY : r.y;
         if (MODE == 1) {
             relax_control(a.ctl, mfin, a.cur);
         } else {
             if (a.maxf_out) *a.maxf_out = mfin;
-            if (a.E_out) *a.E_out = E;
+            if (a.E_out) *a.E_out = r.x;
         }
     }
 }
@@ -280,7 +245,7 @@ __device__ __forceinline__ void finish_reductions(const VertexArgs &a, int nblk,
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_finish(VertexArgs a, int nblk) {
     if (MODE == 1 && a.ctl->done) return;
-    __shared__ double sh[1024 / 64];
+    __shared__ double sh[2 * (1024 / 64)];
     finish_reductions<MODE>(a, nblk, sh, true);
 }
 
@@ -700,8 +665,7 @@ static void eval_impl(const DevTissue &t, const Workspace &w, const void *X, con
     a.ctl = ectl;
     a.epart_cell = w.partials;
     a.n_epart_cell = (int)gc;
-    a.epart_vert = w.partials2;
-    a.mpart = w.mpart;
+    a.part = (double2 *)w.mpart;
     a.finish = gv <= (unsigned)kLastBlockMax;
     a.E_out = E;
     a.maxf_out = maxf;
@@ -732,7 +696,7 @@ static void pass_impl(const DevTissue &t, const Workspace &w, const void *X, con
         VertexArgs a{};
         a.ctl = ectl;
         a.maxf_out = maxf;
-        a.mpart = w.mpart;
+        a.part = (double2 *)w.mpart;
         a.finish = gv <= (unsigned)kLastBlockMax;
         hipLaunchKernelGGL((k_vertex<PosT, M, 0>), dim3(gv), dim3(kBlock), 0, s, t,
                            (const PosT *)X, (PosT *)F, p, (const M *)coeffs_in, a);
@@ -781,7 +745,7 @@ static void relax_iter_impl(const DevTissue &t, const Workspace &w, void *Xc, vo
     a.beta = ra.beta;
     a.Xt = ra.X_target;
     a.g_lin = ra.g_lin;
-    a.mpart = w.mpart;
+    a.part = (double2 *)w.mpart;
     a.finish = gv <= (unsigned)kLastBlockMax;
     hipLaunchKernelGGL((k_vertex<PosT, M, 1>), dim3(gv), dim3(kBlock), 0, s, t,
                        (const PosT *)Xc, (PosT *)Xn, p, (const M *)w.cap, a);

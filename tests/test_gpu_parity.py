@@ -136,14 +136,34 @@ def test_t1_pass_bit_exact_topology(vtx, oracle, mode):
     assert n_sw > 0 and n_st > 0
     T = vtx.Tissue.from_tissue(t)
     Xd = _dev(t.X)
+    # an evaluation before the pass builds the fused evaluation's tile tables
+    T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
     a, b = T.t1(Xd, vtx.Params.from_numpy(p), 0.01, 0.02, mode=mode)
     assert (a, b) == (n_sw, n_st)
     np.testing.assert_array_equal(T.topology(), m.he)
     assert np.abs(Xd.cpu().numpy() - X).max() < 1e-12
     # the staged layouts follow: forces after the pass match the oracle
-    _, F, _ = T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
-    _, Fo = oracle.energy_forces(m, X, p)
+    E, F, _ = T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
+    Eo, Fo = oracle.energy_forces(m, X, p)
     assert _force_err(F.cpu().numpy(), Fo) < 1e-10
+    assert E.item() == pytest.approx(Eo, rel=1e-12)
+
+
+def test_evaluation_after_topology_replaced(vtx, oracle):
+    """set_topology to a T1-edited table: the next evaluation uses it."""
+    t, p = g.workload_single_10k(n_cell=1500, seed=212)
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    n_sw, _ = oracle.t1_pass(m, X, p, 0.01, 0.02)
+    assert n_sw > 0
+    T = vtx.Tissue.from_tissue(t)
+    P = vtx.Params.from_numpy(p)
+    T.energy_forces(_dev(t.X), P, mode="f64")
+    T.set_topology(m.he)
+    E, F, _ = T.energy_forces(_dev(X), P, mode="f64")
+    Eo, Fo = oracle.energy_forces(m, X, p)
+    assert _force_err(F.cpu().numpy(), Fo) < 1e-10
+    assert E.item() == pytest.approx(Eo, rel=1e-12)
 
 
 # ---------------------------------------------------------------- relaxation
@@ -268,7 +288,7 @@ def _batch_case(rng, n, P0):
 
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
-def test_batch_relax_matches_single(vtx, mode):
+def test_batch_relax_matches_single(vtx, oracle, mode):
     """Solid tissues (P0 < 3.8; some converge within the iteration cap, some
     do not yet) plus one fluid tissue (P0 = 3.86) that keeps cycling short
     edges and stops at max_iter: the persistent batch kernel reproduces the
@@ -295,6 +315,15 @@ def test_batch_relax_matches_single(vtx, mode):
         assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
         # the single path sums the line energy from FP32 lengths in MIXED mode
         assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9 if mode == "f64" else 1e-7)
+    # evaluations after the batched T1 passes use the new topologies (at
+    # perturbed positions: equilibrium forces are pure cancellation)
+    for (t, p), X, T in zip(cases, Xs, Ts):
+        m = oracle.Mesh.from_tissue(t)
+        m.he[:] = T.topology()
+        Xh = X.cpu().numpy() + rng.normal(0, 0.02, t.X.shape)
+        _, F, _ = T.energy_forces(_dev(Xh), vtx.Params.from_numpy(p), mode="f64")
+        _, Fo = oracle.energy_forces(m, Xh, p)
+        assert _force_err(F.cpu().numpy(), Fo) < 1e-10
     st = [r["status"] for r in res]
     assert st[0] == 0 and st[2] == 0 and st[4] == 1
 
