@@ -10,8 +10,10 @@ steps are replayed from a captured graph, inputs resident in HBM.
 
 Printed: one JSON line with the whole-job vertex-force evaluations per
 second, the roofline of the dominant kernel (the vertex pass, timed alone
-with HIP events on the stream it is launched on) and the oracle timed on
-the host cores as a CPU baseline.
+with HIP events on the stream it is launched on; also with cold caches,
+after a 512 MiB write evicts the Infinity Cache), the oracle timed on the
+host cores as a CPU baseline, and (unless --no-secondary) the batched
+relaxation and hypergradient measurements.
 """
 from __future__ import annotations
 
@@ -76,6 +78,8 @@ def main():
     ap.add_argument("--batch-max-iter", type=int, default=200000)
     ap.add_argument("--grad-tissues", type=int, default=64)
     ap.add_argument("--plain-sample", type=int, default=2)
+    ap.add_argument("--cold-reps", type=int, default=50,
+                    help="evaluations timed one by one after a 512 MiB cache flush")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate "
                          "hardware traffic counters")
@@ -190,6 +194,34 @@ def main():
         f"cell pass {c_ms * 1e3:.2f} us ({c_gbs:.0f} GB/s)")
     traffic = read_traffic(os.path.join(ROOT, "profiles", "vertex_pass_1m_cells_counters.txt"))
 
+    # ---- cold caches: 512 MiB written between evaluations (not timed), so
+    # that nothing of the ~180 MB an evaluation touches is left in the
+    # 256 MB Infinity Cache or the L2s
+    g1 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g1):
+        one_eval()
+    gv1 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gv1):
+        T.vertex_forces_into(X, cp, coeffs, F2, mode="f32")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
+    def cold(gr, n):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n)]
+        for i, (a, b) in enumerate(evs):
+            flush.fill_(i & 255)
+            a.record()
+            gr.replay()
+            b.record()
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(b) for a, b in evs)[n // 2]  # median, ms
+
+    cold_eval_ms = cold(g1, args.cold_reps)
+    cold_v_ms = cold(gv1, args.cold_reps)
+    del flush, g1, gv1
+    log(f"cold caches: evaluation {cold_eval_ms * 1e3:.2f} us, vertex pass {cold_v_ms * 1e3:.2f} us "
+        f"({vb / (cold_v_ms / 1e3) / 1e9:.0f} GB/s)")
+
     # ---- CPU baseline: the oracle on the same input (FP64 upcast of X)
     cpu = None
     if not args.no_cpu_baseline:
@@ -250,7 +282,10 @@ def main():
                      "frac": v_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": vb, "us_per_launch": v_ms * 1e3,
                      "cell_pass": {"achieved": c_gbs, "bytes_per_launch": cb,
-                                   "us_per_launch": c_ms * 1e3}},
+                                   "us_per_launch": c_ms * 1e3},
+                     "cold_caches": {"vertex_pass_us": cold_v_ms * 1e3,
+                                     "vertex_pass_achieved": vb / (cold_v_ms / 1e3) / 1e9,
+                                     "evaluation_us": cold_eval_ms * 1e3}},
         "cpu_baseline": cpu,
         "secondary": secondary,
     }
