@@ -13,6 +13,10 @@ SOURCES = ["vtx_kernels.hip", "vtx_batch.hip", "vtx_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions (v_pk_*_f32)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no fused multiply-adds chosen by the optimiser: the grid kernels and
+         # the persistent batch kernel inline the same force code in different
+         # surroundings and must round it identically
+         "-ffp-contract=off",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 

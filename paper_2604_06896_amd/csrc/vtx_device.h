@@ -85,48 +85,61 @@ struct Star {
     int nb[3];
 };
 
+// A star is loaded in three stages: (1) the coalesced star entries and the
+// own position, (2) every gather they index, issued before any is used,
+// (3) the arithmetic.
 template <typename PosT, typename M>
-__device__ __forceinline__ void load_star(const DevTissue &t, const PosT *__restrict__ X,
-                                          const DevParams<PosT> &p, const M *__restrict__ cap,
-                                          int v, Star<PosT, M> &s, PosT &xi, PosT &yi) {
-    const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
-    const int nv = t.n_vert;
-    // 1) the star (9 coalesced dword loads) and the own position
+struct StarLoad {
     int32_t w[3], c[3], e[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        w[k] = t.star_nb[k * nv + v];
-        c[k] = t.star_cell[k * nv + v];
-        e[k] = t.star_edge[k * nv + v];
-    }
-    const auto pi = ld2(X, v);
-    // 2) every gather issued before any is used
-    typename Vec2<PosT>::type q[3];
+    typename Vec2<PosT>::type pi, q[3];
     typename Vec2<M>::type cc[3];
     PosT lam[3];
+};
+
+template <typename PosT, typename M>
+__device__ __forceinline__ void star_ids(const DevTissue &t, const PosT *__restrict__ X, int v,
+                                         StarLoad<PosT, M> &L) {
+    const int nv = t.n_vert;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        q[k] = ld2(X, id_of(w[k]));
-        cc[k] = ld2(cap, c[k]);
+        L.w[k] = t.star_nb[k * nv + v];
+        L.c[k] = t.star_cell[k * nv + v];
+        L.e[k] = t.star_edge[k * nv + v];
+    }
+    L.pi = ld2(X, v);
+}
+
+template <typename PosT, typename M>
+__device__ __forceinline__ void star_gather(const PosT *__restrict__ X, const DevParams<PosT> &p,
+                                            const M *__restrict__ cap, StarLoad<PosT, M> &L) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        L.q[k] = ld2(X, id_of(L.w[k]));
+        L.cc[k] = ld2(cap, L.c[k]);
     }
     if (p.lam) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) lam[k] = p.lam[e[k]];
+        for (int k = 0; k < 3; ++k) L.lam[k] = p.lam[L.e[k]];
     } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) lam[k] = p.lam_s;
+        for (int k = 0; k < 3; ++k) L.lam[k] = p.lam_s;
     }
-    xi = pi.x;
-    yi = pi.y;
-    // 3) arithmetic
+}
+
+template <typename PosT, typename M>
+__device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<PosT, M> &L,
+                                          Star<PosT, M> &s, PosT &xi, PosT &yi) {
+    const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
+    xi = L.pi.x;
+    yi = L.pi.y;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        s.nb[k] = id_of(w[k]);
-        s.dx[k] = (M)pdiff<PosT>(q[k].x, pi.x, ox_of(w[k]), Lx);
-        s.dy[k] = (M)pdiff<PosT>(q[k].y, pi.y, oy_of(w[k]), Ly);
-        s.cA[k] = cc[k].x;
-        s.cP[k] = cc[k].y;
-        s.lam[k] = (M)lam[k];
+        s.nb[k] = id_of(L.w[k]);
+        s.dx[k] = (M)pdiff<PosT>(L.q[k].x, L.pi.x, ox_of(L.w[k]), Lx);
+        s.dy[k] = (M)pdiff<PosT>(L.q[k].y, L.pi.y, oy_of(L.w[k]), Ly);
+        s.cA[k] = L.cc[k].x;
+        s.cP[k] = L.cc[k].y;
+        s.lam[k] = (M)L.lam[k];
         const M l = sqrt(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k]);
         // a zero-length edge contributes its minimum-norm subgradient, 0
         const M inv = l > (M)0 ? (M)1 / l : (M)0;
@@ -135,6 +148,16 @@ __device__ __forceinline__ void load_star(const DevTissue &t, const PosT *__rest
         s.ux[k] = s.dx[k] * inv;
         s.uy[k] = s.dy[k] * inv;
     }
+}
+
+template <typename PosT, typename M>
+__device__ __forceinline__ void load_star(const DevTissue &t, const PosT *__restrict__ X,
+                                          const DevParams<PosT> &p, const M *__restrict__ cap,
+                                          int v, Star<PosT, M> &s, PosT &xi, PosT &yi) {
+    StarLoad<PosT, M> L;
+    star_ids<PosT, M>(t, X, v, L);
+    star_gather<PosT, M>(X, p, cap, L);
+    star_math<PosT, M>(t, L, s, xi, yi);
 }
 
 template <typename PosT, typename M>
