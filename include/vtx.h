@@ -80,8 +80,14 @@ extern "C" {
 #define VTX_THETA_P0 1       /* theta = per-cell preferred perimeters P0_c */
 
 /* hypergradient estimators */
+/* Schedules of vtx_batch_relax. */
+#define VTX_SCHED_AUTO (-1)     /* choose by timed trials (vtx_batch_autotune)       */
+#define VTX_SCHED_PERSISTENT 0  /* one persistent launch, one workgroup per tissue   */
+#define VTX_SCHED_GRID 1        /* each tissue in turn on the whole GPU (vtx_relax)  */
+
 #define VTX_GRAD_ADJOINT 0     /* implicit differentiation, adjoint form, CG */
 #define VTX_GRAD_EP_CENTRED 1  /* centred equilibrium propagation            */
+#define VTX_GRAD_EP_FORWARD 2  /* first-order (one-sided) equilibrium propagation */
 
 typedef struct vtx_tissue_s *vtx_tissue;
 typedef struct vtx_batch_s *vtx_batch;
@@ -135,7 +141,7 @@ typedef struct {
 } vtx_relax_result;
 
 typedef struct {
-    int32_t method;        /* VTX_GRAD_ADJOINT or VTX_GRAD_EP_CENTRED */
+    int32_t method;        /* VTX_GRAD_ADJOINT, VTX_GRAD_EP_CENTRED or VTX_GRAD_EP_FORWARD */
     int32_t theta;         /* VTX_THETA_LAMBDA or VTX_THETA_P0 */
     double cg_tol;         /* relative residual |r| / |P b| */
     int64_t cg_max_iter;
@@ -236,6 +242,10 @@ int vtx_hvp(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p, cons
  *     returns (dE/dtheta(X+) - dE/dtheta(X-)) / beta, where C is the v2v
  *     cost to X_target when given (device, element type of X) and the
  *     linear cost dC_dX . X otherwise.
+ *   EP_FORWARD: the first-order estimator: relaxes E + beta C from X_star
+ *     and returns (dE/dtheta(X_beta) - dE/dtheta(X_star)) / beta (bias
+ *     O(beta) against O(beta^2) for the centred one); res->ep_minus is
+ *     zero.
  * The explicit partial d_theta C is not added (zero for costs of X only).
  * dC_dtheta: double device array [n_edge] (lambda) or [n_cell] (P0).
  * `res` is a host struct; synchronises. */
@@ -250,6 +260,22 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
 int vtx_v2v(vtx_tissue t, int32_t mode, const void *X, const void *X_target, double *C_dev,
             double *grad, void *stream);
 
+/* Forward (sensitivity) implicit differentiation along one parameter
+ * direction d (Methods, "Implicit differentiation (ID)": one linear solve
+ * per direction, where the adjoint needs one in total).  Solves
+ *   H w = -(d2E/dX dtheta) d
+ * by CG on the zero-mean subspace (w = dX_star/dtheta . d) and writes the
+ * directional derivative  dC_dX . w  to the double device scalar dC_dd
+ * (the explicit partial d_theta C . d is not added).  d is a double device
+ * array [n_edge] (theta = lambda) or [n_cell] (theta = P0); dC_dX a double
+ * device array [n_vert][2]; dX_dd, if not NULL, receives w (double device
+ * [n_vert][2]).  Only o->theta, o->cg_tol and o->cg_max_iter are read; the
+ * CG iterations, residual and status go to res (host, may be NULL).  Needs
+ * double positions (VTX_F64 or VTX_MIXED).  Synchronises. */
+int vtx_param_sens(vtx_tissue t, int32_t mode, const void *X_star, const vtx_params *p,
+                   const double *d, const double *dC_dX, const vtx_grad_opts *o, double *dC_dd,
+                   double *dX_dd, vtx_grad_result *res, void *stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* Group independent tissues for batched relaxation.  The handles stay
@@ -258,14 +284,34 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out);
 int vtx_batch_destroy(vtx_batch b);
 
 /* Relax every tissue of the batch (each with its own X, parameters and the
- * shared options) in one persistent launch: one workgroup per tissue
- * (schedule 0) or `blocks_per_tissue` cooperating workgroups (schedule 1),
- * tissues taken from a device work queue in descending size.  X and p are
- * host arrays of n entries (device pointers inside).  Results go to the
- * host array res[n]; synchronises.  Nudges are not supported here. */
+ * shared options; Methods, "Simulation engine", per tissue).  Schedules:
+ *   VTX_SCHED_PERSISTENT  one persistent launch captured in a graph, one
+ *                         workgroup of `block_threads` (256, 512 or 1024)
+ *                         threads per tissue looping the whole relaxation,
+ *                         tissues taken from a device work queue in
+ *                         descending size;
+ *   VTX_SCHED_GRID        each tissue in turn through vtx_relax (all
+ *                         workgroups of the GPU on one tissue; suits a few
+ *                         large tissues); block_threads is ignored;
+ *   VTX_SCHED_AUTO        vtx_batch_autotune first, then its choice.
+ * Every schedule gives the same results as vtx_relax on each tissue.  X and
+ * p are host arrays of n entries (device pointers inside).  Results go to
+ * the host array res[n]; synchronises.  Nudges are not supported here. */
 int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
                     const vtx_relax_opts *o, int32_t schedule, int32_t block_threads,
                     vtx_relax_result *res, void *stream);
+
+/* Choose the schedule of vtx_batch_relax for this batch, mode, X, p and o
+ * from timed trials on copies of the positions (T1 off, `trial_iters`
+ * iterations, no convergence test): the persistent schedule with 256, 512
+ * and 1024 threads on all tissues, and the grid schedule on the (up to) two
+ * largest tissues, extrapolated to the batch.  X is not modified; the trial
+ * buffers are allocated and freed here.  Writes the choice to *schedule and
+ * *block_threads and, if trial_ms is not NULL, the four projected times in
+ * milliseconds (persistent 256, 512, 1024, grid).  Synchronises. */
+int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
+                       const vtx_relax_opts *o, int32_t trial_iters, int32_t *schedule,
+                       int32_t *block_threads, double *trial_ms, void *stream);
 
 /* Hypergradients of every tissue of the batch (see vtx_param_grad).
  * ADJOINT: one persistent launch, one workgroup per tissue running the

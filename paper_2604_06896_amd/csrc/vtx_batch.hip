@@ -5,6 +5,7 @@
 // convergence test -- with workgroup barriers only; tissues are taken from a
 // device work queue in descending size so the largest start first.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cstring>
 #include <string>
@@ -614,14 +615,107 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
                     vtx_relax_result *res, void *stream) {
     if (!b || !X || !p || !o || !res) return set_error(VTX_E_ARG, "null argument");
     if (!mode_ok(mode)) return set_error(VTX_E_ARG, "bad precision mode");
-    if (schedule != 0) return set_error(VTX_E_ARG, "only schedule 0 (block per tissue) exists");
-    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
-        return set_error(VTX_E_ARG, "block_threads must be 256, 512 or 1024");
     if (o->beta != 0.0) return set_error(VTX_E_ARG, "batched relaxation takes no nudge");
     int rc = check_relax_opts(o);
     if (rc) return rc;
+    const int n = (int)b->ts.size();
+    for (int i = 0; i < n; ++i)
+        if (!X[i]) return set_error(VTX_E_ARG, "null X in batch");
+    if (schedule == VTX_SCHED_AUTO) {
+        rc = vtx_batch_autotune(b, mode, X, p, o, 0, &schedule, &block_threads, nullptr, stream);
+        if (rc) return rc;
+    }
+    if (schedule == VTX_SCHED_GRID) {
+        for (int i = 0; i < n; ++i)
+            if ((rc = vtx_relax(b->ts[i], mode, X[i], &p[i], o, &res[i], stream))) return rc;
+        return VTX_OK;
+    }
+    if (schedule != VTX_SCHED_PERSISTENT) return set_error(VTX_E_ARG, "unknown schedule");
+    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return set_error(VTX_E_ARG, "block_threads must be 256, 512 or 1024");
     return batch_relax_run(b, mode, X, p, o, nullptr, nullptr, 0.0, block_threads, res,
                            (hipStream_t)stream);
+}
+
+int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
+                       const vtx_relax_opts *o, int32_t trial_iters, int32_t *schedule,
+                       int32_t *block_threads, double *trial_ms, void *stream) {
+    if (!b || !X || !p || !o || !schedule || !block_threads)
+        return set_error(VTX_E_ARG, "null argument");
+    if (!mode_ok(mode)) return set_error(VTX_E_ARG, "bad precision mode");
+    const int n = (int)b->ts.size();
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t iters = trial_iters > 0 ? trial_iters : 200;
+    vtx_relax_opts to = *o;
+    to.t1_enable = 0;
+    to.tol = 0.0;
+    to.patience = 1;
+    to.max_iter = iters;
+    to.beta = 0.0;
+    to.X_target = nullptr;
+    to.g_lin = nullptr;
+    int rc = check_relax_opts(&to);
+    if (rc) return rc;
+    // trial copies of every tissue's positions
+    const size_t elt = mode == VTX_F32 ? sizeof(float) : sizeof(double);
+    std::vector<size_t> bytes(n);
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!X[i]) return set_error(VTX_E_ARG, "null X in batch");
+        bytes[i] = (size_t)tissue_size(b->ts[i]) * 2 * elt;
+        total += (bytes[i] + 255) & ~(size_t)255;
+    }
+    char *buf = nullptr;
+    hipError_t e = hipMalloc((void **)&buf, total);
+    if (e != hipSuccess) return hip_fail(e);
+    std::vector<void *> Xc(n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        Xc[i] = buf + off;
+        off += (bytes[i] + 255) & ~(size_t)255;
+    }
+    std::vector<vtx_relax_result> res(n);
+    auto reset = [&]() -> hipError_t {
+        for (int i = 0; i < n; ++i) {
+            const hipError_t ee = hipMemcpyAsync(Xc[i], X[i], bytes[i], hipMemcpyDeviceToDevice, s);
+            if (ee != hipSuccess) return ee;
+        }
+        return hipStreamSynchronize(s);
+    };
+    auto now = []() { return std::chrono::steady_clock::now(); };
+    double ms[4] = {0, 0, 0, 0};
+    const int threads[3] = {256, 512, 1024};
+    for (int k = 0; k < 3 && rc == VTX_OK; ++k) {
+        if ((e = reset()) != hipSuccess) break;
+        const auto t0 = now();
+        rc = batch_relax_run(b, mode, Xc.data(), p, &to, nullptr, nullptr, 0.0, threads[k],
+                             res.data(), s);
+        ms[k] = std::chrono::duration<double, std::milli>(now() - t0).count();
+    }
+    if (rc == VTX_OK && e == hipSuccess) {
+        // grid schedule: the two largest tissues, scaled to the batch
+        const int m = n < 2 ? n : 2;
+        double t = 0.0;
+        for (int j = 0; j < m && rc == VTX_OK; ++j) {
+            const int i = b->order[j];
+            if ((e = reset()) != hipSuccess) break;
+            const auto t0 = now();
+            rc = vtx_relax(b->ts[i], mode, Xc[i], &p[i], &to, &res[i], stream);
+            t += std::chrono::duration<double, std::milli>(now() - t0).count();
+        }
+        ms[3] = t / m * n;
+    }
+    (void)hipFree(buf);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e);
+    int best = 0;
+    for (int k = 1; k < 4; ++k)
+        if (ms[k] < ms[best]) best = k;
+    *schedule = best == 3 ? VTX_SCHED_GRID : VTX_SCHED_PERSISTENT;
+    *block_threads = best == 3 ? 0 : threads[best];
+    if (trial_ms)
+        for (int k = 0; k < 4; ++k) trial_ms[k] = ms[k];
+    return VTX_OK;
 }
 
 int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const vtx_params *p,
@@ -677,7 +771,9 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         return e == hipSuccess ? VTX_OK : hip_fail(e);
     }
-    if (o->method != VTX_GRAD_EP_CENTRED) return set_error(VTX_E_ARG, "unknown method");
+    if (o->method != VTX_GRAD_EP_CENTRED && o->method != VTX_GRAD_EP_FORWARD)
+        return set_error(VTX_E_ARG, "unknown method");
+    const bool centred = o->method == VTX_GRAD_EP_CENTRED;
     if (!(o->beta != 0.0)) return set_error(VTX_E_ARG, "EP needs beta != 0");
     if (o->ep_relax.t1_enable) return set_error(VTX_E_ARG, "EP relaxations cannot use T1");
     int rc = check_relax_opts(&o->ep_relax);
@@ -695,12 +791,16 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         if (e != hipSuccess) return hip_fail(e);
     }
     std::vector<vtx_relax_result> rp(n), rm(n);
+    // first-order EP: one relaxation nudged by beta; the other state stays X*
     rc = batch_relax_run(b, mode, Xp.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
-                         0.5 * o->beta, block_threads, rp.data(), s);
+                         centred ? 0.5 * o->beta : o->beta, block_threads, rp.data(), s);
     if (rc) return rc;
-    rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
-                         -0.5 * o->beta, block_threads, rm.data(), s);
-    if (rc) return rc;
+    if (centred) {
+        rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target,
+                             X_target ? nullptr : dC_dX, -0.5 * o->beta, block_threads, rm.data(),
+                             s);
+        if (rc) return rc;
+    }
     for (int i = 0; i < n; ++i) items[i].X = Xp[i];
     e = hipMemcpyAsync(b->gitems, items.data(), sizeof(GradItem) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)

@@ -22,6 +22,7 @@ CONVERGED, NOT_CONVERGED, CG_NEG_CURVATURE, CG_MAXITER = 0, 1, 2, 3
 F32, F64, MIXED = 0, 1, 2
 THETA_LAMBDA, THETA_P0 = 0, 1
 GRAD_ADJOINT, GRAD_EP_CENTRED = 0, 1
+SCHED_AUTO, SCHED_PERSISTENT, SCHED_GRID = -1, 0, 1
 
 _MODE_NAMES = {"f32": F32, "f64": F64, "mixed": MIXED}
 
@@ -95,6 +96,8 @@ def lib():
                                      P(_GradResult), vp]
         L.vtx_v2v.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         if hasattr(L, "vtx_batch_create"):
+            L.vtx_batch_autotune.argtypes = [vp, i32, P(vp), P(_Params), P(_RelaxOpts), i32,
+                                             P(i32), P(i32), P(d), vp]
             L.vtx_batch_create.argtypes = [P(vp), i32, P(vp)]
             L.vtx_batch_destroy.argtypes = [vp]
             L.vtx_batch_relax.argtypes = [vp, i32, P(vp), P(_Params), P(_RelaxOpts), i32, i32,
@@ -356,8 +359,7 @@ class Batch:
         except Exception:
             pass
 
-    def relax(self, Xs, params_list, mode="mixed", schedule=0, block_threads=256, **opts):
-        m = _mode(mode)
+    def _marshal(self, Xs, params_list, m):
         n = len(self.tissues)
         assert len(Xs) == n and len(params_list) == n
         keep = []
@@ -369,11 +371,32 @@ class Batch:
             keep.append(kp)
             cps[k] = cp
         xs = (C.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        return xs, cps, keep
+
+    def relax(self, Xs, params_list, mode="mixed", schedule=SCHED_PERSISTENT, block_threads=256,
+              **opts):
+        """schedule: SCHED_PERSISTENT (one workgroup of `block_threads` per
+        tissue), SCHED_GRID (each tissue in turn on the whole GPU) or
+        SCHED_AUTO (timed trials pick one)."""
+        m = _mode(mode)
+        xs, cps, keep = self._marshal(Xs, params_list, m)
         o = relax_opts(**opts)
-        res = (_RelaxResult * n)()
+        res = (_RelaxResult * len(self.tissues))()
         _check(lib().vtx_batch_relax(self._h, m, xs, cps, C.byref(o), int(schedule),
                                      int(block_threads), res, _stream()))
         return [r.as_dict() for r in res]
+
+    def autotune(self, Xs, params_list, mode="mixed", trial_iters=200, **opts):
+        """(schedule, block_threads, projected trial times in ms for persistent
+        256/512/1024 and grid); Xs are not modified."""
+        m = _mode(mode)
+        xs, cps, keep = self._marshal(Xs, params_list, m)
+        o = relax_opts(**opts)
+        sch, bt = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 4)()
+        _check(lib().vtx_batch_autotune(self._h, m, xs, cps, C.byref(o), int(trial_iters),
+                                        C.byref(sch), C.byref(bt), ms, _stream()))
+        return sch.value, bt.value, list(ms)
 
     def param_grad(self, Xs, params_list, dC_dX=None, X_target=None, method="adjoint",
                    theta="lambda", mode="f64", cg_tol=1e-8, cg_max_iter=100000, beta=1e-3,

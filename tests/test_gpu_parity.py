@@ -347,6 +347,39 @@ def test_split_passes_equal_full_evaluation(vtx, oracle):
     np.testing.assert_allclose(cf[:, 1], 2 * p.KP * (P_ - p.P0), rtol=1e-10, atol=1e-13)
 
 
+def test_batch_schedules_agree(vtx):
+    """The persistent schedule (256 and 1024 threads per tissue), the grid
+    schedule and the autotuned choice give the same relaxations."""
+    rng = np.random.default_rng(43)
+    cases = [_batch_case(rng, n, P0) for n, P0 in ((64, 3.65), (200, 3.70), (120, 3.68))]
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=20000, t1_enable=True, l_min=0.01)
+    runs = []
+    for sched, bt in ((vtx.SCHED_PERSISTENT, 256), (vtx.SCHED_PERSISTENT, 1024),
+                      (vtx.SCHED_GRID, 256), (vtx.SCHED_AUTO, 256)):
+        Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
+        Xs = [_dev(t.X) for t, _ in cases]
+        B = vtx.Batch(Ts)
+        ps = [vtx.Params.from_numpy(p) for _, p in cases]
+        if sched == vtx.SCHED_AUTO:
+            X0 = [X.clone() for X in Xs]
+            sch, bt_best, ms = B.autotune(Xs, ps, mode="mixed", trial_iters=100, **opts)
+            print("autotune", sch, bt_best, ms)
+            assert sch in (vtx.SCHED_PERSISTENT, vtx.SCHED_GRID)
+            assert bt_best in ((256, 512, 1024) if sch == vtx.SCHED_PERSISTENT else (0,))
+            assert all(m > 0 for m in ms)
+            assert all(torch.equal(a, b) for a, b in zip(X0, Xs))  # trials leave X alone
+        res = B.relax(Xs, ps, mode="mixed", schedule=sched, block_threads=bt, **opts)
+        runs.append((res, [X.cpu().numpy() for X in Xs], [T.topology() for T in Ts]))
+    ref = runs[0]
+    for res, Xh, he in runs[1:]:
+        for r0, r, x0, x, h0, h in zip(ref[0], res, ref[1], Xh, ref[2], he):
+            assert (r["status"], r["iters"], r["n_t1"], r["n_stretch"]) == \
+                (r0["status"], r0["iters"], r0["n_t1"], r0["n_stretch"])
+            np.testing.assert_array_equal(h, h0)
+            assert np.abs(x - x0).max() < 1e-9
+            assert r["energy"] == pytest.approx(r0["energy"], rel=1e-7)
+
+
 # --------------------------------------------------- batched hypergradients
 
 @pytest.fixture(scope="module")
