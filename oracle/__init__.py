@@ -321,3 +321,51 @@ def ep_grad(mesh, X_star, params, X_target, beta, theta="lambda", **relax_kw):
     else:
         raise ValueError(theta)
     return g, dict(plus=rp, minus=rm, X_plus=Xp, X_minus=Xm)
+
+
+def ep_grad_forward(mesh, X_star, params, X_target, beta, theta="lambda", **relax_kw):
+    """First-order EP (Methods, EP): relax E + beta C from X*, then
+    (dE/dtheta(X_beta) - dE/dtheta(X*)) / beta; bias O(beta)."""
+    mp = mesh.copy()
+    Xp = _f64(X_star).copy()
+    rp = relax(mp, Xp, params, beta=beta, X_target=X_target, **relax_kw)
+    if theta == "lambda":
+        g = (edge_lengths(mp, Xp) - edge_lengths(mesh, X_star)) / beta
+    elif theta == "P0":
+        KP = np.broadcast_to(params.KP, (mesh.n_cell,))
+        _, Pp, _ = cells(mp, Xp)
+        _, P0, _ = cells(mesh, X_star)
+        g = -2.0 * KP * (Pp - P0) / beta
+    else:
+        raise ValueError(theta)
+    return g, dict(plus=rp, X_plus=Xp)
+
+
+def sens_derivative(mesh, X, params, d, dC_dX, theta="lambda", tol=1e-8, maxit=100000):
+    """Forward implicit differentiation along a parameter direction d
+    (Methods, ID): H w = -(d2E/dX dtheta) d, then dC/dtheta . d = grad_X C . w.
+    The right-hand side is a force of modified parameters: for theta =
+    lambda the force of tensions d alone (K_A = K_P = 0); for theta = P0
+    minus the force of perimeter coefficients 2 K_P d (K_A = 0, lambda = 0,
+    P0 = P(X) - d, so that 2 K_P (P - P0) = 2 K_P d)."""
+    nc, ne = mesh.n_cell, mesh.n_edge
+    d = np.asarray(d, dtype=np.float64)
+    q = params.copy()
+    q.KA = np.zeros(nc)
+    q.A0 = np.broadcast_to(params.A0, (nc,)).copy()
+    if theta == "lambda":
+        q.KP = np.zeros(nc)
+        q.P0 = np.broadcast_to(params.P0, (nc,)).copy()
+        q.lam = d.copy()
+        _, rhs = energy_forces(mesh, X, q)
+    elif theta == "P0":
+        _, P, _ = cells(mesh, X)
+        q.KP = np.broadcast_to(params.KP, (nc,)).copy()
+        q.P0 = P - d
+        q.lam = np.zeros(ne)
+        _, F = energy_forces(mesh, X, q)
+        rhs = -F
+    else:
+        raise ValueError(theta)
+    w, info = cg(mesh, X, params, rhs, tol, maxit)
+    return float(np.sum(_f64(dC_dX) * w)), w, info

@@ -593,7 +593,8 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
         r.cg_iters = h.cg_iter;
         r.cg_rel_res = h.rel_res;
         r.status = h.status;
-    } else if (o->method == VTX_GRAD_EP_CENTRED) {
+    } else if (o->method == VTX_GRAD_EP_CENTRED || o->method == VTX_GRAD_EP_FORWARD) {
+        const bool centred = o->method == VTX_GRAD_EP_CENTRED;
         if (!(o->beta != 0.0)) return fail(VTX_E_ARG, "EP needs beta != 0");
         if (o->ep_relax.t1_enable) return fail(VTX_E_ARG, "EP relaxations cannot use T1");
         if (!X_target && !dC_dX) return fail(VTX_E_ARG, "EP needs X_target or dC_dX");
@@ -604,10 +605,12 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
         vtx_relax_opts ro = o->ep_relax;
         ro.X_target = X_target;
         ro.g_lin = X_target ? nullptr : dC_dX;
-        ro.beta = 0.5 * o->beta;
+        ro.beta = centred ? 0.5 * o->beta : o->beta;
         if ((rc = relax_impl(t, mode, Xp, p, &ro, &r.ep_plus, s))) return rc;
-        ro.beta = -0.5 * o->beta;
-        if ((rc = relax_impl(t, mode, Xm, p, &ro, &r.ep_minus, s))) return rc;
+        if (centred) {
+            ro.beta = -0.5 * o->beta;
+            if ((rc = relax_impl(t, mode, Xm, p, &ro, &r.ep_minus, s))) return rc;
+        }
         launch_ep(t->d, mode, Xp, Xm, raw(p), o->theta, o->beta, dC_dtheta, s);
         if ((rc = check_launch("EP estimate"))) return rc;
         HIPCHK(hipStreamSynchronize(s));
@@ -616,6 +619,52 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
         return fail(VTX_E_ARG, "unknown hypergradient method");
     }
     if (res) *res = r;
+    return VTX_OK;
+}
+
+int vtx_param_sens(vtx_tissue t, int32_t mode, const void *X_star, const vtx_params *p,
+                   const double *d, const double *dC_dX, const vtx_grad_opts *o, double *dC_dd,
+                   double *dX_dd, vtx_grad_result *res, void *stream) {
+    if (!t || !X_star || !p || !d || !dC_dX || !o || !dC_dd || !mode_ok(mode))
+        return fail(VTX_E_ARG, "bad argument");
+    if (mode == VTX_F32) return fail(VTX_E_ARG, "sensitivities need double positions");
+    if (o->theta != VTX_THETA_LAMBDA && o->theta != VTX_THETA_P0)
+        return fail(VTX_E_ARG, "unknown theta selector");
+    if (!(o->cg_tol > 0) || o->cg_max_iter < 1) return fail(VTX_E_ARG, "bad CG options");
+    hipStream_t s = (hipStream_t)stream;
+    const int nv = (int)t->n_vert;
+    double *rhs = t->ep_buf;  // [n_vert][2]
+    launch_sens_rhs(t->d, t->w, X_star, raw(p), o->theta, d, rhs, s);
+    launch_cell_coeffs(t->d, t->w, mode, X_star, raw(p), s);
+    LoopCtl c{};
+    c.status = VTX_CG_MAXITER;
+    c.tol = o->cg_tol;
+    c.max_iter = o->cg_max_iter;
+    int rc;
+    if ((rc = reset_ctl(t, 0, c, s))) return rc;
+    launch_cg_init(t->w, nv, rhs, s);
+    if ((rc = check_launch("sensitivity CG init"))) return rc;
+    if ((rc = read_ctl(t, 0, s))) return rc;
+    if (!t->w.ctl_host[0].done) {
+        rc = run_loop(t, 32, o->cg_max_iter, s, [&](int, hipStream_t cs) {
+            launch_cg_iter(t->d, t->w, mode, X_star, raw(p), cs);
+        });
+        if (rc) return rc;
+    }
+    const LoopCtl &h = t->w.ctl_host[0];
+    launch_project(t->w, nv, t->w.cg, s);
+    launch_dot_pos(t->w, VTX_F64, nv, dC_dX, t->w.cg, dC_dd, s);
+    if (dX_dd)
+        HIPCHK(hipMemcpyAsync(dX_dd, t->w.cg, 16 * (size_t)nv, hipMemcpyDeviceToDevice, s));
+    if ((rc = check_launch("sensitivity"))) return rc;
+    HIPCHK(hipStreamSynchronize(s));
+    if (res) {
+        vtx_grad_result r{};
+        r.cg_iters = h.cg_iter;
+        r.cg_rel_res = h.rel_res;
+        r.status = h.status;
+        *res = r;
+    }
     return VTX_OK;
 }
 

@@ -549,6 +549,35 @@ __global__ __launch_bounds__(kBlock) void k_ep_p0(DevTissue t, const PosT *Xp, c
     g[c] = -2.0 * (double)p.kp(c) * (pp - pm) / beta;
 }
 
+// Sensitivity right-hand side -(d2E/dX dtheta) d for a parameter direction
+// d.  theta = lambda: the line term's mixed derivative along d is the
+// gradient of sum_e d_e l_e, so the RHS is the force of tensions d alone.
+// theta = P0: d/dP0_c of 2K_P (P_c - P0_c) grad P_c is -2K_P grad P_c, so the
+// RHS is minus the force of perimeter coefficients cP_c = 2K_P d_c alone.
+// k_sens_cap writes those per-cell coefficients (cA = 0), k_sens_rhs forms
+// the vertex force from them with the shared force code.
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_sens_cap(DevTissue t, DevParams<PosT> p,
+                                                     const double *d, int theta, double *cap) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= t.n_cell) return;
+    st2(cap, c, 0.0, theta == VTX_THETA_P0 ? 2.0 * (double)p.kp(c) * d[c] : 0.0);
+}
+
+template <typename PosT>
+__global__ __launch_bounds__(kBlock) void k_sens_rhs(DevTissue t, const PosT *X,
+                                                     DevParams<PosT> p, const double *cap,
+                                                     double sgn, double *rhs) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= t.n_vert) return;
+    Star<PosT, double> s;
+    PosT xi, yi;
+    load_star<PosT, double>(t, X, p, cap, v, s, xi, yi);
+    double fx, fy;
+    star_force<PosT, double>(s, fx, fy);
+    st2(rhs, v, sgn * fx, sgn * fy);
+}
+
 // v2v cost and gradient (minimum image).
 template <typename PosT>
 __global__ __launch_bounds__(kBlock) void k_v2v(DevTissue t, const PosT *X, const PosT *Xt,
@@ -908,6 +937,20 @@ void launch_v2v(const DevTissue &t, const Workspace &w, int mode, const void *X,
     else
         hipLaunchKernelGGL((k_v2v<double>), dim3(gv), dim3(kBlock), 0, s, t, (const double *)X,
                            (const double *)Xt, grad, w.partials2, w.ctl + 1, C);
+}
+
+void launch_sens_rhs(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                     int theta, const double *d, double *rhs, hipStream_t s) {
+    // double positions only (VTX_F64 / VTX_MIXED)
+    DevParams<double> p = dev_params<double>(pr);
+    hipLaunchKernelGGL(k_sens_cap<double>, dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t, p,
+                       d, theta, w.cell_aux);
+    DevParams<double> q = p;
+    q.lam = theta == VTX_THETA_LAMBDA ? d : nullptr;
+    q.lam_s = 0.0;
+    hipLaunchKernelGGL(k_sens_rhs<double>, dim3(blocks_for(t.n_vert)), dim3(kBlock), 0, s, t,
+                       (const double *)X, q, (const double *)w.cell_aux,
+                       theta == VTX_THETA_LAMBDA ? 1.0 : -1.0, rhs);
 }
 
 void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const void *X,

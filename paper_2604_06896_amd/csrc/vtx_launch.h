@@ -37,6 +37,8 @@ void launch_cell_coeffs(const DevTissue &t, const Workspace &w, int mode, const 
 void launch_hvp(const DevTissue &t, const Workspace &w, int mode, const void *X,
                 const ParamsRaw &p, const double *v, double *Hv, double *dpart, LoopCtl *ctl,
                 hipStream_t s);
+void launch_sens_rhs(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
+                     int theta, const double *d, double *rhs, hipStream_t s);
 void launch_cg_init(const Workspace &w, int nv, const double *b, hipStream_t s);
 void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
                     const ParamsRaw &p, hipStream_t s);

@@ -21,7 +21,9 @@ OK, E_ARG, E_TOPOLOGY, E_CAPACITY, E_HIP, E_NONFINITE = 0, -1, -2, -3, -4, -5
 CONVERGED, NOT_CONVERGED, CG_NEG_CURVATURE, CG_MAXITER = 0, 1, 2, 3
 F32, F64, MIXED = 0, 1, 2
 THETA_LAMBDA, THETA_P0 = 0, 1
-GRAD_ADJOINT, GRAD_EP_CENTRED = 0, 1
+GRAD_ADJOINT, GRAD_EP_CENTRED, GRAD_EP_FORWARD = 0, 1, 2
+_METHODS = {"adjoint": GRAD_ADJOINT, "ep": GRAD_EP_CENTRED, "ep_centred": GRAD_EP_CENTRED,
+            "ep_forward": GRAD_EP_FORWARD}
 SCHED_AUTO, SCHED_PERSISTENT, SCHED_GRID = -1, 0, 1
 
 _MODE_NAMES = {"f32": F32, "f64": F64, "mixed": MIXED}
@@ -95,6 +97,8 @@ def lib():
         L.vtx_param_grad.argtypes = [vp, i32, vp, P(_Params), vp, vp, P(_GradOpts), vp,
                                      P(_GradResult), vp]
         L.vtx_v2v.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.vtx_param_sens.argtypes = [vp, i32, vp, P(_Params), vp, vp, P(_GradOpts), vp, vp,
+                                     P(_GradResult), vp]
         if hasattr(L, "vtx_batch_create"):
             L.vtx_batch_autotune.argtypes = [vp, i32, P(vp), P(_Params), P(_RelaxOpts), i32,
                                              P(i32), P(i32), P(d), vp]
@@ -322,7 +326,7 @@ class Tissue:
         m = self._xcheck(X_star, mode)
         p, keep = params.to_c(X_star.dtype, X_star.device)
         th = THETA_LAMBDA if theta == "lambda" else THETA_P0
-        meth = GRAD_ADJOINT if method == "adjoint" else GRAD_EP_CENTRED
+        meth = _METHODS[method]
         n = self.n_edge if th == THETA_LAMBDA else self.n_cell
         out = torch.empty(n, dtype=torch.float64, device=X_star.device)
         if dC_dX is not None:
@@ -336,6 +340,27 @@ class Tissue:
         info = dict(cg_iters=r.cg_iters, cg_rel_res=r.cg_rel_res, status=r.status,
                     ep_plus=r.ep_plus.as_dict(), ep_minus=r.ep_minus.as_dict())
         return out, info
+
+    def param_sens(self, X_star, params, d, dC_dX, theta="lambda", mode="f64", cg_tol=1e-8,
+                   cg_max_iter=100000, want_dX=False):
+        """Forward implicit differentiation along the parameter direction d:
+        returns (dC_dX . dX*/dtheta . d  as a 0-d device tensor,
+        dX*/dtheta . d or None, info)."""
+        m = self._xcheck(X_star, mode)
+        p, keep = params.to_c(X_star.dtype, X_star.device)
+        th = THETA_LAMBDA if theta == "lambda" else THETA_P0
+        d = d.to(device=X_star.device, dtype=torch.float64).contiguous()
+        dC_dX = dC_dX.to(device=X_star.device, dtype=torch.float64).contiguous()
+        if d.numel() != (self.n_edge if th == THETA_LAMBDA else self.n_cell):
+            raise ValueError("d has the wrong length for theta")
+        out = torch.empty((), dtype=torch.float64, device=X_star.device)
+        w = torch.empty((self.n_vert, 2), dtype=torch.float64, device=X_star.device) \
+            if want_dX else None
+        o = _GradOpts(GRAD_ADJOINT, th, float(cg_tol), int(cg_max_iter), 0.0, relax_opts())
+        r = _GradResult()
+        _check(lib().vtx_param_sens(self._h, m, _ptr(X_star), C.byref(p), _ptr(d), _ptr(dC_dX),
+                                    C.byref(o), _ptr(out), _ptr(w), C.byref(r), _stream()))
+        return out, w, dict(cg_iters=r.cg_iters, cg_rel_res=r.cg_rel_res, status=r.status)
 
 
 class Batch:
@@ -425,7 +450,7 @@ class Batch:
         xt = None
         if X_target is not None:
             xt = (C.c_void_p * n)(*[x.data_ptr() for x in X_target])
-        meth = GRAD_ADJOINT if method == "adjoint" else GRAD_EP_CENTRED
+        meth = _METHODS[method]
         ro = relax_opts(**(ep_relax or {}))
         o = _GradOpts(meth, th, float(cg_tol), int(cg_max_iter), float(beta), ro)
         res = (_GradResult * n)()

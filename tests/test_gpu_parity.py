@@ -278,6 +278,45 @@ def test_ep_gradient_f64(vtx, oracle, equilibrium):
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
 
 
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_sensitivity_f64(vtx, oracle, equilibrium, theta, mode):
+    """Forward ID along a random direction: value and dX*/dtheta . d against
+    the oracle, and against the library's own adjoint gradient . d."""
+    t, m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    rng = np.random.default_rng(23)
+    d = rng.normal(size=m.n_edge if theta == "lambda" else m.n_cell)
+    so, wo, info_o = oracle.sens_derivative(m, X, p, d, b, theta=theta, tol=1e-10)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    P = vtx.Params.from_numpy(p)
+    # MIXED runs the HVP with FP32 force arithmetic: its CG floors near 1e-7
+    # and meets spurious non-positive curvature below that, so it solves to 1e-5
+    s, w, info = T.param_sens(_dev(X), P, _dev(d), _dev(b), theta=theta, mode=mode,
+                              cg_tol=1e-10 if mode == "f64" else 1e-5, want_dX=True)
+    assert info["status"] == 0
+    tol = 1e-7 if mode == "f64" else 1e-3
+    if mode == "f64":
+        assert abs(info["cg_iters"] - info_o["iters"]) <= 2
+    assert s.item() == pytest.approx(so, rel=tol)
+    assert np.abs(w.cpu().numpy() - wo).max() < tol * np.abs(wo).max()
+    gg, _ = T.param_grad(_dev(X), P, dC_dX=_dev(b), theta=theta, cg_tol=1e-10)
+    assert s.item() == pytest.approx(float(gg.cpu().numpy() @ d), rel=10 * tol)
+
+
+def test_ep_forward_gradient_f64(vtx, oracle, equilibrium):
+    t, m, X, p, Xt = equilibrium
+    beta = 0.04
+    go, _ = oracle.ep_grad_forward(m, X, p, Xt, beta, eta=3e-3, tol=1e-12, patience=1,
+                                   max_iter=400000)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    gg, info = T.param_grad(_dev(X), vtx.Params.from_numpy(p), X_target=_dev(Xt),
+                            method="ep_forward", beta=beta,
+                            ep_relax=dict(eta=3e-3, tol=1e-12, max_iter=400000))
+    assert info["status"] == 0 and info["ep_minus"]["iters"] == 0
+    assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+
+
 # ------------------------------------------------------------------- batched
 
 def _batch_case(rng, n, P0):
@@ -420,18 +459,19 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, 
         assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
 
 
-def test_batch_ep_matches_single(vtx, oracle, small_equilibria):
+@pytest.mark.parametrize("method", ["ep", "ep_forward"])
+def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method):
     beta = 0.04
     ep = dict(eta=3e-3, tol=1e-12, max_iter=400000)
     Ts, Xs, Ps, Xts, refs = [], [], [], [], []
     for t, m, X, p, Xt in small_equilibria:
         T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
-        gs, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), X_target=_dev(Xt), method="ep",
+        gs, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), X_target=_dev(Xt), method=method,
                              beta=beta, ep_relax=ep)
         Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); Xts.append(_dev(Xt))
         refs.append(gs.cpu().numpy())
     B = vtx.Batch(Ts)
-    outs, infos = B.param_grad(Xs, Ps, X_target=Xts, method="ep", beta=beta, ep_relax=ep)
+    outs, infos = B.param_grad(Xs, Ps, X_target=Xts, method=method, beta=beta, ep_relax=ep)
     for gsingle, gb, inf in zip(refs, outs, infos):
         assert inf["status"] == 0
         assert inf["ep_plus"]["iters"] > 1

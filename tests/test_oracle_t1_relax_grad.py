@@ -271,3 +271,50 @@ def test_centred_ep_converges_to_adjoint_at_second_order(oracle, equilibrium):
     # beta / 2.5: O(beta^2) shrinks the error 6.25x, O(beta) only 2.5x
     assert errs[1] < errs[0] / 4
     assert errs[1] < 1e-3 * np.abs(g_adj).max()
+
+
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_sensitivity_matches_finite_differences_and_adjoint(oracle, equilibrium, theta):
+    """Forward ID along d (one solve per direction) against central
+    differences of the relaxed cost, and against the adjoint gradient . d
+    (a different linear solve and a different mixed-derivative code path)."""
+    m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    rng = np.random.default_rng(22)
+    n = m.n_edge if theta == "lambda" else m.n_cell
+    d = rng.normal(size=n)
+    d /= np.linalg.norm(d)
+    s, w, info = oracle.sens_derivative(m, X, p, d, b, theta=theta, tol=1e-12)
+    assert info["status"] == 0
+    assert abs(w.mean(axis=0)).max() < 1e-12          # solved on the zero-mean subspace
+    gr, _ = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-12)
+    assert s == pytest.approx(gr @ d, rel=1e-8)
+    hh = 5e-4
+    pp, pm = p.copy(), p.copy()
+    if theta == "lambda":
+        pp.lam, pm.lam = p.lam + hh * d, p.lam - hh * d
+    else:
+        pp.P0, pm.P0 = p.P0 + hh * d, p.P0 - hh * d
+    fd = (_relaxed_cost(oracle, m, X, pp, Xt) - _relaxed_cost(oracle, m, X, pm, Xt)) / (2 * hh)
+    assert s == pytest.approx(fd, rel=2e-3)
+    # w is the directional derivative of the equilibrium itself
+    Xp, Xm = X.copy(), X.copy()
+    oracle.relax(m.copy(), Xp, pp, eta=3e-3, tol=1e-12, patience=1, max_iter=400000)
+    oracle.relax(m.copy(), Xm, pm, eta=3e-3, tol=1e-12, patience=1, max_iter=400000)
+    dX = (Xp - Xm) / (2 * hh)
+    dX -= dX.mean(axis=0)
+    assert np.abs(dX - w).max() < 5e-3 * np.abs(w).max()
+
+
+def test_forward_ep_converges_to_adjoint_at_first_order(oracle, equilibrium):
+    m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    g_adj, _ = oracle.adjoint_grad(m, X, p, b, tol=1e-12)
+    errs = []
+    for beta in (1e-1, 4e-2):
+        g_ep, info = oracle.ep_grad_forward(m, X, p, Xt, beta, eta=3e-3, tol=1e-12,
+                                            patience=1, max_iter=400000)
+        assert info["plus"]["status"] == 0
+        errs.append(np.abs(g_ep - g_adj).max())
+    # beta / 2.5: an O(beta) bias shrinks about 2.5x (the centred one 6.25x)
+    assert 1.8 < errs[0] / errs[1] < 3.5
