@@ -90,3 +90,11 @@ def test_four_valent_vertex_rejected(libvtx):
     he[he[:, 4] == w, 4] = v
     rc, msg = _create(libvtx, he, t.n_vert, t.n_cell)
     assert rc == -2, msg
+
+
+def test_logistic_fit_recovers_transition():
+    from paper_2604_06896_amd.studies import fit_logistic
+    p0 = np.linspace(3.6, 4.1, 11)
+    frac = 1.0 / (1.0 + np.exp(-(p0 - 3.83) / 0.03))
+    pc, w = fit_logistic(p0, frac)
+    assert pc == pytest.approx(3.83, abs=1e-6) and w == pytest.approx(0.03, rel=1e-5)
