@@ -101,6 +101,8 @@ def lib():
         L.ora_relax.argtypes = [mp, dp, pp, P(_RelaxOpts), P(_RelaxOut)]
         L.ora_cg.restype = C.c_int
         L.ora_cg.argtypes = [mp, dp, pp, dp, C.c_double, C.c_int64, dp, P(C.c_int64), dp]
+        L.ora_minres.restype = C.c_int
+        L.ora_minres.argtypes = [mp, dp, pp, dp, C.c_double, C.c_int64, dp, P(C.c_int64), dp]
         _lib = L
     return _lib
 
@@ -287,10 +289,22 @@ def cg(mesh, X, params, b, tol=1e-8, maxit=100000):
     return mu, dict(status=st, iters=it.value, rel_res=rr.value)
 
 
+def minres(mesh, X, params, b, tol=1e-8, maxit=100000):
+    X, b = _f64(X), _f64(b)
+    x = np.empty_like(X)
+    it = C.c_int64(0)
+    rr = C.c_double(0.0)
+    ph = _ParHold(mesh, params)
+    m = mesh._c()
+    st = lib().ora_minres(C.byref(m), _dptr(X), C.byref(ph.c), _dptr(b), float(tol), int(maxit),
+                          _dptr(x), C.byref(it), C.byref(rr))
+    return x, dict(status=st, iters=it.value, rel_res=rr.value)
+
+
 def adjoint_grad(mesh, X, params, dC_dX, theta="lambda", tol=1e-8, maxit=100000,
-                 dC_dtheta=None):
+                 dC_dtheta=None, solver="cg"):
     """grad_theta C = d_theta C - M^T mu,  H mu = grad_X C  (Methods, ID)."""
-    mu, info = cg(mesh, X, params, dC_dX, tol, maxit)
+    mu, info = (cg if solver == "cg" else minres)(mesh, X, params, dC_dX, tol, maxit)
     if theta == "lambda":
         g = -mixed_lambda(mesh, X, mu)
     elif theta == "P0":
@@ -341,7 +355,8 @@ def ep_grad_forward(mesh, X_star, params, X_target, beta, theta="lambda", **rela
     return g, dict(plus=rp, X_plus=Xp)
 
 
-def sens_derivative(mesh, X, params, d, dC_dX, theta="lambda", tol=1e-8, maxit=100000):
+def sens_derivative(mesh, X, params, d, dC_dX, theta="lambda", tol=1e-8, maxit=100000,
+                    solver="cg"):
     """Forward implicit differentiation along a parameter direction d
     (Methods, ID): H w = -(d2E/dX dtheta) d, then dC/dtheta . d = grad_X C . w.
     The right-hand side is a force of modified parameters: for theta =
@@ -367,5 +382,5 @@ def sens_derivative(mesh, X, params, d, dC_dX, theta="lambda", tol=1e-8, maxit=1
         rhs = -F
     else:
         raise ValueError(theta)
-    w, info = cg(mesh, X, params, rhs, tol, maxit)
+    w, info = (cg if solver == "cg" else minres)(mesh, X, params, rhs, tol, maxit)
     return float(np.sum(_f64(dC_dX) * w)), w, info

@@ -657,3 +657,73 @@ int ora_cg(const ora_mesh *m, const double *X, const ora_par *p, const double *b
     free(r); free(q); free(Aq);
     return status;
 }
+
+/* MINRES (Paige and Saunders' minimum-residual Krylov method; the paper's
+ * solver for the possibly indefinite Hessian) on H x = P b from x = 0.
+ * Lanczos vectors q_k from q_1 = P b / |P b|:
+ *   beta_{k+1} q_{k+1} = H q_k - alpha_k q_k - beta_k q_{k-1},
+ *   alpha_k = q_k . H q_k,
+ * build a tridiagonal T_k; x_k minimises |P b - H x| over the Krylov space,
+ * found by reducing T_k to upper-triangular form with one Givens rotation
+ * per step (the new column meets the two previous rotations first) and
+ * updating x along search directions w_k (three-term recurrence).  The
+ * residual norm |phi_k| follows from the rotations.  Stops when
+ * |phi_k| <= tol |P b| (status 0), when the Lanczos process ends
+ * (beta_{k+1} = 0: the Krylov space is invariant, the residual is minimal;
+ * status 0 if small enough, else 3) or after maxit iterations (status 3).
+ * The solution is projected to zero mean. */
+int ora_minres(const ora_mesh *m, const double *X, const ora_par *p, const double *b,
+               double tol, int64_t maxit, double *x, int64_t *iters, double *rel_res)
+{
+    int64_t nv = m->n_vert, n = 2 * nv;
+    double *q = malloc(sizeof(double) * n), *qp = malloc(sizeof(double) * n);
+    double *z = malloc(sizeof(double) * n);
+    double *w1 = malloc(sizeof(double) * n), *w2 = malloc(sizeof(double) * n);
+    memcpy(q, b, sizeof(double) * n);
+    project_zero_mean(q, nv);
+    double beta1 = sqrt(dot(q, q, n));
+    for (int64_t k = 0; k < n; ++k) {
+        x[k] = 0.0; qp[k] = 0.0; w1[k] = 0.0; w2[k] = 0.0;
+        if (beta1 > 0.0) q[k] /= beta1;
+    }
+    double beta = 0.0;               /* T's off-diagonal entry linking q_{k-1}, q_k */
+    double c1 = 1.0, s1 = 0.0;       /* rotation of the previous step */
+    double c2 = 1.0, s2 = 0.0;       /* rotation two steps back */
+    double phibar = beta1;
+    int status = beta1 > 0.0 ? 3 : 0;
+    int64_t it = 0;
+    while (status == 3 && it < maxit) {
+        ora_hvp(m, X, p, q, z);
+        double alpha = dot(q, z, n);
+        for (int64_t k = 0; k < n; ++k) z[k] -= alpha * q[k] + beta * qp[k];
+        double beta_next = sqrt(dot(z, z, n));
+        /* the new column (beta, alpha, beta_next) meets the old rotations */
+        double eps = s2 * beta;
+        double dbar = c2 * beta;
+        double delta = c1 * dbar + s1 * alpha;
+        double gbar = -s1 * dbar + c1 * alpha;
+        double gamma = sqrt(gbar * gbar + beta_next * beta_next);
+        if (gamma == 0.0) break;     /* singular T: nothing more to gain */
+        double c = gbar / gamma, s = beta_next / gamma;
+        double tau = c * phibar;
+        phibar = -s * phibar;
+        for (int64_t k = 0; k < n; ++k) {
+            double w = (q[k] - delta * w1[k] - eps * w2[k]) / gamma;
+            x[k] += tau * w;
+            w2[k] = w1[k];
+            w1[k] = w;
+            qp[k] = q[k];
+            q[k] = beta_next > 0.0 ? z[k] / beta_next : 0.0;
+        }
+        c2 = c1; s2 = s1; c1 = c; s1 = s;
+        beta = beta_next;
+        ++it;
+        if (fabs(phibar) <= tol * beta1) status = 0;
+        else if (beta_next == 0.0) break;
+    }
+    project_zero_mean(x, nv);
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = beta1 > 0.0 ? fabs(phibar) / beta1 : 0.0;
+    free(q); free(qp); free(z); free(w1); free(w2);
+    return status;
+}

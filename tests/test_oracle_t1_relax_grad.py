@@ -318,3 +318,41 @@ def test_forward_ep_converges_to_adjoint_at_first_order(oracle, equilibrium):
         errs.append(np.abs(g_ep - g_adj).max())
     # beta / 2.5: an O(beta) bias shrinks about 2.5x (the centred one 6.25x)
     assert 1.8 < errs[0] / errs[1] < 3.5
+
+
+def _exact_hessian(oracle, m, X, p):
+    n = X.size
+    return np.column_stack([oracle.hvp(m, X, p, np.eye(n)[k].reshape(X.shape)).ravel()
+                            for k in range(n)])
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_minres_solves_indefinite_systems(oracle, seed):
+    """At an unrelaxed Voronoi state H is strongly indefinite: CG stops on
+    negative curvature, MINRES still returns the pseudo-inverse solution."""
+    rng = np.random.default_rng(seed)
+    t = g.random_tissue(20, np.sqrt(20.0), rng=rng)
+    p = g.uniform_params(t, P0=3.75)
+    p.lam = rng.uniform(0.05, 0.15, t.n_edge)
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    H = _exact_hessian(oracle, m, X, p)
+    ev = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert ev[0] < -1.0                                  # indefinite
+    b = rng.normal(size=X.shape)
+    x, info = oracle.minres(m, X, p, b, tol=1e-13)
+    assert info["status"] == 0 and info["rel_res"] < 1e-13
+    ref = (np.linalg.pinv(H, rcond=1e-10) @ (b - b.mean(axis=0)).ravel()).reshape(X.shape)
+    assert np.abs(x - ref).max() < 1e-9 * np.abs(ref).max()
+    _, info_cg = oracle.cg(m, X, p, b, tol=1e-13)
+    assert info_cg["status"] == 2                        # CG_NEG_CURVATURE
+
+
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_minres_adjoint_equals_cg_adjoint_at_equilibrium(oracle, equilibrium, theta):
+    m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    g_cg, i_cg = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-12)
+    g_mr, i_mr = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-12, solver="minres")
+    assert i_cg["status"] == 0 and i_mr["status"] == 0
+    assert np.abs(g_mr - g_cg).max() < 1e-9 * np.abs(g_cg).max()
