@@ -88,6 +88,7 @@ extern "C" {
 #define VTX_GRAD_ADJOINT 0     /* implicit differentiation, adjoint form, CG */
 #define VTX_GRAD_EP_CENTRED 1  /* centred equilibrium propagation            */
 #define VTX_GRAD_EP_FORWARD 2  /* first-order (one-sided) equilibrium propagation */
+#define VTX_GRAD_ADJOINT_MINRES 3 /* implicit differentiation, adjoint form, MINRES */
 
 typedef struct vtx_tissue_s *vtx_tissue;
 typedef struct vtx_batch_s *vtx_batch;
@@ -141,7 +142,7 @@ typedef struct {
 } vtx_relax_result;
 
 typedef struct {
-    int32_t method;        /* VTX_GRAD_ADJOINT, VTX_GRAD_EP_CENTRED or VTX_GRAD_EP_FORWARD */
+    int32_t method;        /* VTX_GRAD_ADJOINT(_MINRES), VTX_GRAD_EP_CENTRED or _FORWARD */
     int32_t theta;         /* VTX_THETA_LAMBDA or VTX_THETA_P0 */
     double cg_tol;         /* relative residual |r| / |P b| */
     int64_t cg_max_iter;
@@ -238,6 +239,10 @@ int vtx_hvp(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p, cons
  *     (P removes the per-component mean; rigid translations are null
  *     vectors of H) and returns  dC_dtheta = -(d2E/dX dtheta)^T mu.
  *     dC_dX is a double device array [n_vert][2] (the backward of any cost).
+ *     CG stops with VTX_CG_NEG_CURVATURE if H is not positive definite.
+ *   ADJOINT_MINRES: the same with MINRES (Paige-Saunders; the paper's
+ *     solver, Methods, ID), which needs H symmetric only; cg_tol bounds the
+ *     recursive residual |P b - H mu| / |P b|.
  *   EP_CENTRED: relaxes E + (beta/2) C and E - (beta/2) C from X_star and
  *     returns (dE/dtheta(X+) - dE/dtheta(X-)) / beta, where C is the v2v
  *     cost to X_target when given (device, element type of X) and the
@@ -269,8 +274,9 @@ int vtx_v2v(vtx_tissue t, int32_t mode, const void *X, const void *X_target, dou
  * (the explicit partial d_theta C . d is not added).  d is a double device
  * array [n_edge] (theta = lambda) or [n_cell] (theta = P0); dC_dX a double
  * device array [n_vert][2]; dX_dd, if not NULL, receives w (double device
- * [n_vert][2]).  Only o->theta, o->cg_tol and o->cg_max_iter are read; the
- * CG iterations, residual and status go to res (host, may be NULL).  Needs
+ * [n_vert][2]).  Only o->theta, o->cg_tol, o->cg_max_iter and o->method
+ * (VTX_GRAD_ADJOINT_MINRES selects MINRES, anything else CG) are read; the
+ * iterations, residual and status go to res (host, may be NULL).  Needs
  * double positions (VTX_F64 or VTX_MIXED).  Synchronises. */
 int vtx_param_sens(vtx_tissue t, int32_t mode, const void *X_star, const vtx_params *p,
                    const double *d, const double *dC_dX, const vtx_grad_opts *o, double *dC_dd,

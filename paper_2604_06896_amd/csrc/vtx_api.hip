@@ -416,7 +416,7 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
     A((void **)&w.mpart, 16 * (size_t)nb);
     A((void **)&w.t1_list, 4 * (size_t)t1cap);
     A((void **)&w.ctl, 2 * sizeof(LoopCtl));
-    A((void **)&w.cg, 8 * 8 * (size_t)n_vert);
+    A((void **)&w.cg, 6 * 16 * (size_t)n_vert);  // CG: 4 vectors, MINRES: 6
     A((void **)&w.scal, 16 * sizeof(double));
     A((void **)&t->ep_buf, 2 * 16 * (size_t)n_vert);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.ctl_host, 2 * sizeof(LoopCtl), 0);
@@ -556,6 +556,39 @@ int vtx_v2v(vtx_tissue t, int32_t mode, const void *X, const void *X_target, dou
     return check_launch("vtx_v2v");
 }
 
+// Solves H x = P b at X (H restricted to the zero-mean subspace) by CG or
+// MINRES on the device, x left projected in the first workspace vector.
+static int solve_hessian(vtx_tissue t, int mode, const void *X, const vtx_params *p,
+                         const double *b, bool minres, double tol, int64_t max_iter,
+                         hipStream_t s, vtx_grad_result *r) {
+    const int nv = (int)t->n_vert;
+    launch_cell_coeffs(t->d, t->w, mode, X, raw(p), s);
+    LoopCtl c{};
+    c.status = VTX_CG_MAXITER;
+    c.tol = tol;
+    c.max_iter = max_iter;
+    c.solver = minres ? 1 : 0;
+    int rc;
+    if ((rc = reset_ctl(t, 0, c, s))) return rc;
+    if (minres) launch_minres_init(t->w, nv, b, s);
+    else launch_cg_init(t->w, nv, b, s);
+    if ((rc = check_launch("Krylov init"))) return rc;
+    if ((rc = read_ctl(t, 0, s))) return rc;
+    if (!t->w.ctl_host[0].done) {
+        rc = run_loop(t, 32, max_iter, s, [&](int, hipStream_t cs) {
+            if (minres) launch_minres_iter(t->d, t->w, mode, X, raw(p), cs);
+            else launch_cg_iter(t->d, t->w, mode, X, raw(p), cs);
+        });
+        if (rc) return rc;
+    }
+    const LoopCtl &h = t->w.ctl_host[0];
+    launch_project(t->w, nv, t->w.cg, s);
+    r->cg_iters = h.cg_iter;
+    r->cg_rel_res = h.rel_res;
+    r->status = h.status;
+    return check_launch("Krylov solve");
+}
+
 int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_params *p,
                    const double *dC_dX, const void *X_target, const vtx_grad_opts *o,
                    double *dC_dtheta, vtx_grad_result *res, void *stream) {
@@ -566,33 +599,15 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
     hipStream_t s = (hipStream_t)stream;
     vtx_grad_result r{};
     int rc;
-    if (o->method == VTX_GRAD_ADJOINT) {
+    if (o->method == VTX_GRAD_ADJOINT || o->method == VTX_GRAD_ADJOINT_MINRES) {
         if (!dC_dX) return fail(VTX_E_ARG, "the adjoint needs dC_dX");
-        if (!(o->cg_tol > 0) || o->cg_max_iter < 1) return fail(VTX_E_ARG, "bad CG options");
-        const int nv = (int)t->n_vert;
-        launch_cell_coeffs(t->d, t->w, mode, X_star, raw(p), s);
-        LoopCtl c{};
-        c.status = VTX_CG_MAXITER;
-        c.tol = o->cg_tol;
-        c.max_iter = o->cg_max_iter;
-        if ((rc = reset_ctl(t, 0, c, s))) return rc;
-        launch_cg_init(t->w, nv, dC_dX, s);
-        if ((rc = check_launch("CG init"))) return rc;
-        if ((rc = read_ctl(t, 0, s))) return rc;
-        if (!t->w.ctl_host[0].done) {
-            rc = run_loop(t, 32, o->cg_max_iter, s, [&](int, hipStream_t cs) {
-                launch_cg_iter(t->d, t->w, mode, X_star, raw(p), cs);
-            });
-            if (rc) return rc;
-        }
-        const LoopCtl &h = t->w.ctl_host[0];
-        launch_project(t->w, nv, t->w.cg, s);
+        if (!(o->cg_tol > 0) || o->cg_max_iter < 1) return fail(VTX_E_ARG, "bad Krylov options");
+        if ((rc = solve_hessian(t, mode, X_star, p, dC_dX, o->method == VTX_GRAD_ADJOINT_MINRES,
+                                o->cg_tol, o->cg_max_iter, s, &r)))
+            return rc;
         launch_contract(t->d, mode, X_star, raw(p), o->theta, t->w.cg, dC_dtheta, s);
         if ((rc = check_launch("adjoint contraction"))) return rc;
         HIPCHK(hipStreamSynchronize(s));
-        r.cg_iters = h.cg_iter;
-        r.cg_rel_res = h.rel_res;
-        r.status = h.status;
     } else if (o->method == VTX_GRAD_EP_CENTRED || o->method == VTX_GRAD_EP_FORWARD) {
         const bool centred = o->method == VTX_GRAD_EP_CENTRED;
         if (!(o->beta != 0.0)) return fail(VTX_E_ARG, "EP needs beta != 0");
@@ -635,36 +650,16 @@ int vtx_param_sens(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
     const int nv = (int)t->n_vert;
     double *rhs = t->ep_buf;  // [n_vert][2]
     launch_sens_rhs(t->d, t->w, X_star, raw(p), o->theta, d, rhs, s);
-    launch_cell_coeffs(t->d, t->w, mode, X_star, raw(p), s);
-    LoopCtl c{};
-    c.status = VTX_CG_MAXITER;
-    c.tol = o->cg_tol;
-    c.max_iter = o->cg_max_iter;
-    int rc;
-    if ((rc = reset_ctl(t, 0, c, s))) return rc;
-    launch_cg_init(t->w, nv, rhs, s);
-    if ((rc = check_launch("sensitivity CG init"))) return rc;
-    if ((rc = read_ctl(t, 0, s))) return rc;
-    if (!t->w.ctl_host[0].done) {
-        rc = run_loop(t, 32, o->cg_max_iter, s, [&](int, hipStream_t cs) {
-            launch_cg_iter(t->d, t->w, mode, X_star, raw(p), cs);
-        });
-        if (rc) return rc;
-    }
-    const LoopCtl &h = t->w.ctl_host[0];
-    launch_project(t->w, nv, t->w.cg, s);
+    vtx_grad_result r{};
+    int rc = solve_hessian(t, mode, X_star, p, rhs, o->method == VTX_GRAD_ADJOINT_MINRES,
+                           o->cg_tol, o->cg_max_iter, s, &r);
+    if (rc) return rc;
     launch_dot_pos(t->w, VTX_F64, nv, dC_dX, t->w.cg, dC_dd, s);
     if (dX_dd)
         HIPCHK(hipMemcpyAsync(dX_dd, t->w.cg, 16 * (size_t)nv, hipMemcpyDeviceToDevice, s));
     if ((rc = check_launch("sensitivity"))) return rc;
     HIPCHK(hipStreamSynchronize(s));
-    if (res) {
-        vtx_grad_result r{};
-        r.cg_iters = h.cg_iter;
-        r.cg_rel_res = h.rel_res;
-        r.status = h.status;
-        *res = r;
-    }
+    if (res) *res = r;
     return VTX_OK;
 }
 

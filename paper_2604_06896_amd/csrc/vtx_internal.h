@@ -83,6 +83,12 @@ struct LoopCtl {
     // CG scalars
     double rr, rr0, pAp, alpha, beta_cg, rel_res;
     int64_t cg_iter;
+    // MINRES scalars (solver 1): Lanczos off-diagonal, the two previous
+    // Givens rotations, the residual recurrence, and the step's update
+    int32_t solver;                // 0: CG (curvature check in the HVP), 1: MINRES
+    int32_t mr_noop;               // the update kernel of this step has nothing to do
+    double mr_beta1, mr_beta, mr_c1, mr_s1, mr_c2, mr_s2, mr_phibar;
+    double mr_delta, mr_eps, mr_gamma, mr_tau, mr_beta_next;
 };
 
 struct Workspace {

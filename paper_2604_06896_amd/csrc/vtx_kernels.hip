@@ -330,11 +330,13 @@ __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *
             const double pAp = block_sum_array(dpart, gridDim.x, 1, sh);
             if (threadIdx.x == 0) {
                 ctl->pAp = pAp;
-                if (!(pAp > 0.0)) {
-                    ctl->done = 1;
-                    ctl->status = VTX_CG_NEG_CURVATURE;
-                } else {
-                    ctl->alpha = ctl->rr / pAp;
+                if (ctl->solver == 0) {  // CG: stop on non-positive curvature
+                    if (!(pAp > 0.0)) {
+                        ctl->done = 1;
+                        ctl->status = VTX_CG_NEG_CURVATURE;
+                    } else {
+                        ctl->alpha = ctl->rr / pAp;
+                    }
                 }
             }
         }
@@ -662,6 +664,158 @@ __global__ __launch_bounds__(kBlock) void k_mean_pos(const PosT *a, int nv, doub
     }
 }
 
+// ----------------------------------------------------------------- MINRES
+// Minimum-residual Krylov solve of H x = P b for symmetric, possibly
+// indefinite H (Paige and Saunders; the paper's solver for implicit
+// differentiation).  Vectors (double [n_vert][2]) in the CG workspace:
+// x, q (Lanczos vector q_k), qp (q_{k-1}), z (H q_k, then the next Lanczos
+// direction), w1, w2 (the two previous search directions).  One step:
+// z = H q with alpha = q.Hq fused into the HVP (k_hvp_vertex), then
+// k_mr_lanczos (z -= alpha q + beta qp, beta' = |z|, the Givens rotation of
+// the new tridiagonal column and the residual recurrence, in the last
+// block), then k_mr_update (new search direction, x step, next q).
+struct MinresVecs {
+    double *x, *q, *qp, *z, *w1, *w2;
+};
+
+// z = P b (b minus its mean) into q, |P b|^2 -> beta1 and the initial state.
+__global__ __launch_bounds__(kBlock) void k_mr_init(const double *__restrict__ b, int nv,
+                                                    const double *mean, MinresVecs m,
+                                                    double *__restrict__ part, LoopCtl *ctl) {
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    double ss = 0.0;
+    if (v < nv) {
+        const int64_t k = 2 * (int64_t)v;
+        const double rx = b[k] - mean[0], ry = b[k + 1] - mean[1];
+        m.q[k] = rx;
+        m.q[k + 1] = ry;
+        ss = rx * rx + ry * ry;
+    }
+    const double bs = block_sum(ss, sh);
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        s_last = last_block(&ctl->arrive);
+    }
+    __syncthreads();
+    if (s_last) {
+        const double s2 = block_sum_array(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            const double b1 = sqrt(s2);
+            ctl->mr_beta1 = b1;
+            ctl->mr_phibar = b1;
+            ctl->mr_beta = 0.0;
+            ctl->mr_c1 = ctl->mr_c2 = 1.0;
+            ctl->mr_s1 = ctl->mr_s2 = 0.0;
+            ctl->mr_noop = 1;
+            ctl->rel_res = b1 > 0.0 ? 1.0 : 0.0;
+            if (!(b1 > 0.0)) {
+                ctl->done = 1;
+                ctl->status = VTX_CONVERGED;
+            }
+        }
+    }
+}
+
+// q /= beta1; x = qp = w1 = w2 = 0.
+__global__ __launch_bounds__(kBlock) void k_mr_init2(int nv, MinresVecs m, const LoopCtl *ctl) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const double b1 = ctl->mr_beta1;
+    const double inv = b1 > 0.0 ? 1.0 / b1 : 0.0;
+    for (int c = 0; c < 2; ++c) {
+        const int64_t k = 2 * (int64_t)v + c;
+        m.q[k] *= inv;
+        m.x[k] = m.qp[k] = m.w1[k] = m.w2[k] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mr_lanczos(int nv, MinresVecs m,
+                                                       double *__restrict__ part, LoopCtl *ctl) {
+    if (ctl->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->mr_noop = 1;
+        return;
+    }
+    __shared__ double sh[kBlock / 64];
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    const double alpha = ctl->pAp, beta = ctl->mr_beta;
+    double ss = 0.0;
+    if (v < nv) {
+        for (int c = 0; c < 2; ++c) {
+            const int64_t k = 2 * (int64_t)v + c;
+            const double zk = m.z[k] - (alpha * m.q[k] + beta * m.qp[k]);
+            m.z[k] = zk;
+            ss += zk * zk;
+        }
+    }
+    const double bs = block_sum(ss, sh);
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        s_last = last_block(&ctl->arrive);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    const double s2 = block_sum_array(part, gridDim.x, 1, sh);
+    if (threadIdx.x != 0) return;
+    const double beta_next = sqrt(s2);
+    // the new tridiagonal column (beta, alpha, beta_next) meets the two
+    // previous rotations, then a new rotation removes beta_next
+    const double eps = ctl->mr_s2 * beta;
+    const double dbar = ctl->mr_c2 * beta;
+    const double delta = ctl->mr_c1 * dbar + ctl->mr_s1 * alpha;
+    const double gbar = -ctl->mr_s1 * dbar + ctl->mr_c1 * alpha;
+    const double gamma = sqrt(gbar * gbar + beta_next * beta_next);
+    ctl->cg_iter += 1;
+    if (!(gamma > 0.0)) {  // singular tridiagonal: no further progress
+        ctl->mr_noop = 1;
+        ctl->done = 1;
+        ctl->status = ctl->rel_res <= ctl->tol ? VTX_CONVERGED : VTX_CG_MAXITER;
+        return;
+    }
+    const double c = gbar / gamma, s = beta_next / gamma;
+    ctl->mr_delta = delta;
+    ctl->mr_eps = eps;
+    ctl->mr_gamma = gamma;
+    ctl->mr_tau = c * ctl->mr_phibar;
+    ctl->mr_beta_next = beta_next;
+    ctl->mr_phibar = -s * ctl->mr_phibar;
+    ctl->mr_c2 = ctl->mr_c1;
+    ctl->mr_s2 = ctl->mr_s1;
+    ctl->mr_c1 = c;
+    ctl->mr_s1 = s;
+    ctl->mr_beta = beta_next;
+    ctl->mr_noop = 0;
+    const double rel = fabs(ctl->mr_phibar) / ctl->mr_beta1;
+    ctl->rel_res = rel;
+    if (rel <= ctl->tol) {
+        ctl->done = 1;
+        ctl->status = VTX_CONVERGED;
+    } else if (!(beta_next > 0.0) || ctl->cg_iter >= ctl->max_iter) {
+        ctl->done = 1;
+        ctl->status = VTX_CG_MAXITER;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mr_update(int nv, MinresVecs m, const LoopCtl *ctl) {
+    if (ctl->mr_noop) return;
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const double delta = ctl->mr_delta, eps = ctl->mr_eps, gamma = ctl->mr_gamma;
+    const double tau = ctl->mr_tau, bn = ctl->mr_beta_next;
+    for (int c = 0; c < 2; ++c) {
+        const int64_t k = 2 * (int64_t)v + c;
+        const double qk = m.q[k];
+        const double w = (qk - delta * m.w1[k] - eps * m.w2[k]) / gamma;
+        m.x[k] += tau * w;
+        m.w2[k] = m.w1[k];
+        m.w1[k] = w;
+        m.qp[k] = qk;
+        m.q[k] = bn > 0.0 ? m.z[k] / bn : 0.0;
+    }
+}
+
 // ================================================================ launchers
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -864,6 +1018,32 @@ void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void
     hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, x, r, (const double *)q,
                        (const double *)Aq, nv, w.partials, w.ctl);
     hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(kBlock), 0, s, (const double *)r, q, nv, w.ctl);
+}
+
+static MinresVecs minres_vecs(const Workspace &w, int nv) {
+    const int64_t n = 2 * (int64_t)nv;
+    return MinresVecs{w.cg, w.cg + n, w.cg + 2 * n, w.cg + 3 * n, w.cg + 4 * n, w.cg + 5 * n};
+}
+
+void launch_minres_init(const Workspace &w, int nv, const double *b, hipStream_t s) {
+    const unsigned gv = blocks_for(nv);
+    const unsigned gm = gv < 1024 ? gv : 1024;
+    const MinresVecs m = minres_vecs(w, nv);
+    hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, b, nv, w.partials2, w.ctl,
+                       w.scal);
+    hipLaunchKernelGGL(k_mr_init, dim3(gv), dim3(kBlock), 0, s, b, nv, (const double *)w.scal,
+                       m, w.partials, w.ctl);
+    hipLaunchKernelGGL(k_mr_init2, dim3(gv), dim3(kBlock), 0, s, nv, m, (const LoopCtl *)w.ctl);
+}
+
+void launch_minres_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                        const ParamsRaw &p, hipStream_t s) {
+    const int nv = t.n_vert;
+    const MinresVecs m = minres_vecs(w, nv);
+    launch_hvp(t, w, mode, X, p, m.q, m.z, w.partials, w.ctl, s);
+    const unsigned gv = blocks_for(nv);
+    hipLaunchKernelGGL(k_mr_lanczos, dim3(gv), dim3(kBlock), 0, s, nv, m, w.partials, w.ctl);
+    hipLaunchKernelGGL(k_mr_update, dim3(gv), dim3(kBlock), 0, s, nv, m, (const LoopCtl *)w.ctl);
 }
 
 void launch_project(const Workspace &w, int nv, double *x, hipStream_t s) {

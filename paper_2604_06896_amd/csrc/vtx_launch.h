@@ -39,6 +39,9 @@ void launch_hvp(const DevTissue &t, const Workspace &w, int mode, const void *X,
                 hipStream_t s);
 void launch_sens_rhs(const DevTissue &t, const Workspace &w, const void *X, const ParamsRaw &pr,
                      int theta, const double *d, double *rhs, hipStream_t s);
+void launch_minres_init(const Workspace &w, int nv, const double *b, hipStream_t s);
+void launch_minres_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
+                        const ParamsRaw &p, hipStream_t s);
 void launch_cg_init(const Workspace &w, int nv, const double *b, hipStream_t s);
 void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
                     const ParamsRaw &p, hipStream_t s);

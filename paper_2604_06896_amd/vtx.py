@@ -21,9 +21,9 @@ OK, E_ARG, E_TOPOLOGY, E_CAPACITY, E_HIP, E_NONFINITE = 0, -1, -2, -3, -4, -5
 CONVERGED, NOT_CONVERGED, CG_NEG_CURVATURE, CG_MAXITER = 0, 1, 2, 3
 F32, F64, MIXED = 0, 1, 2
 THETA_LAMBDA, THETA_P0 = 0, 1
-GRAD_ADJOINT, GRAD_EP_CENTRED, GRAD_EP_FORWARD = 0, 1, 2
-_METHODS = {"adjoint": GRAD_ADJOINT, "ep": GRAD_EP_CENTRED, "ep_centred": GRAD_EP_CENTRED,
-            "ep_forward": GRAD_EP_FORWARD}
+GRAD_ADJOINT, GRAD_EP_CENTRED, GRAD_EP_FORWARD, GRAD_ADJOINT_MINRES = 0, 1, 2, 3
+_METHODS = {"adjoint": GRAD_ADJOINT, "adjoint_minres": GRAD_ADJOINT_MINRES,
+            "ep": GRAD_EP_CENTRED, "ep_centred": GRAD_EP_CENTRED, "ep_forward": GRAD_EP_FORWARD}
 SCHED_AUTO, SCHED_PERSISTENT, SCHED_GRID = -1, 0, 1
 
 _MODE_NAMES = {"f32": F32, "f64": F64, "mixed": MIXED}
@@ -342,7 +342,7 @@ class Tissue:
         return out, info
 
     def param_sens(self, X_star, params, d, dC_dX, theta="lambda", mode="f64", cg_tol=1e-8,
-                   cg_max_iter=100000, want_dX=False):
+                   cg_max_iter=100000, want_dX=False, solver="cg"):
         """Forward implicit differentiation along the parameter direction d:
         returns (dC_dX . dX*/dtheta . d  as a 0-d device tensor,
         dX*/dtheta . d or None, info)."""
@@ -356,7 +356,8 @@ class Tissue:
         out = torch.empty((), dtype=torch.float64, device=X_star.device)
         w = torch.empty((self.n_vert, 2), dtype=torch.float64, device=X_star.device) \
             if want_dX else None
-        o = _GradOpts(GRAD_ADJOINT, th, float(cg_tol), int(cg_max_iter), 0.0, relax_opts())
+        meth = GRAD_ADJOINT_MINRES if solver == "minres" else GRAD_ADJOINT
+        o = _GradOpts(meth, th, float(cg_tol), int(cg_max_iter), 0.0, relax_opts())
         r = _GradResult()
         _check(lib().vtx_param_sens(self._h, m, _ptr(X_star), C.byref(p), _ptr(d), _ptr(dC_dX),
                                     C.byref(o), _ptr(out), _ptr(w), C.byref(r), _stream()))

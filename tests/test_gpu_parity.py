@@ -266,6 +266,47 @@ def test_adjoint_gradient_f64(vtx, oracle, equilibrium, theta):
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-7 * np.abs(go).max()
 
 
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_adjoint_minres_f64(vtx, oracle, equilibrium, theta):
+    t, m, X, p, Xt = equilibrium
+    _, b = oracle.v2v(m, X, Xt)
+    go, info_o = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10, solver="minres")
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    gg, info = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=_dev(b), theta=theta,
+                            method="adjoint_minres", cg_tol=1e-10)
+    assert info["status"] == 0 and info_o["status"] == 0
+    assert abs(info["cg_iters"] - info_o["iters"]) <= 2
+    assert info["cg_rel_res"] <= 1e-10
+    assert np.abs(gg.cpu().numpy() - go).max() < 1e-7 * np.abs(go).max()
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_minres_sensitivity_at_indefinite_state(vtx, oracle, seed):
+    """At an unrelaxed Voronoi state (H strongly indefinite) CG stops on
+    negative curvature on both sides; MINRES matches the oracle's MINRES."""
+    rng = np.random.default_rng(seed)
+    t = g.random_tissue(20, np.sqrt(20.0), rng=rng)
+    p = g.uniform_params(t, P0=3.75)
+    p.lam = rng.uniform(0.05, 0.15, t.n_edge)
+    m = oracle.Mesh.from_tissue(t)
+    b = rng.normal(size=t.X.shape)
+    d = rng.normal(size=t.n_edge)
+    so, wo, io = oracle.sens_derivative(m, t.X, p, d, b, tol=1e-11, solver="minres")
+    assert io["status"] == 0
+    T = vtx.Tissue.from_tissue(t)
+    P = vtx.Params.from_numpy(p)
+    s, w, info = T.param_sens(_dev(t.X), P, _dev(d), _dev(b), cg_tol=1e-11, want_dX=True,
+                              solver="minres")
+    # Lanczos loses orthogonality over ~200 steps on this system, so the
+    # summation order (the GPU's fixed tree against the oracle's loop) moves
+    # the stopping step by a few percent
+    assert info["status"] == 0 and abs(info["cg_iters"] - io["iters"]) <= 0.1 * io["iters"]
+    assert s.item() == pytest.approx(so, rel=1e-7)
+    assert np.abs(w.cpu().numpy() - wo).max() < 1e-7 * np.abs(wo).max()
+    _, _, info_cg = T.param_sens(_dev(t.X), P, _dev(d), _dev(b), cg_tol=1e-11)
+    assert info_cg["status"] == vtx.CG_NEG_CURVATURE
+
+
 def test_ep_gradient_f64(vtx, oracle, equilibrium):
     t, m, X, p, Xt = equilibrium
     beta = 0.04
