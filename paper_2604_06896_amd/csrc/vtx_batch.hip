@@ -72,6 +72,7 @@ struct GradOpts {
     double tol;
     int64_t max_iter;
     int theta;
+    int minres;  // 0: CG, 1: MINRES
 };
 
 struct BatchOpts {
@@ -161,7 +162,6 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
             st2(cap, c, (M)((PosT)2 * p.ka(c) * (A - p.a0(c))),
                 (M)((PosT)2 * p.kp(c) * (P - p.p0(c))));
         }
-        // r = P b, q = r, x = 0
         double sx = 0.0, sy = 0.0;
         for (int v = threadIdx.x; v < nv; v += blockDim.x) {
             sx += G.b[2 * (int64_t)v];
@@ -169,60 +169,136 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
         }
         const double mbx = bsum_bcast(sx, sh, &s_bc) / (double)nv;
         const double mby = bsum_bcast(sy, sh, &s_bc) / (double)nv;
-        double rr = 0.0;
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-            const double r0 = G.b[2 * (int64_t)v] - mbx, r1 = G.b[2 * (int64_t)v + 1] - mby;
-            r[2 * (int64_t)v] = r0;
-            r[2 * (int64_t)v + 1] = r1;
-            q[2 * (int64_t)v] = r0;
-            q[2 * (int64_t)v + 1] = r1;
-            x[2 * (int64_t)v] = 0.0;
-            x[2 * (int64_t)v + 1] = 0.0;
-            rr += r0 * r0 + r1 * r1;
-        }
-        rr = bsum_bcast(rr, sh, &s_bc);
-        const double rr0 = rr;
-        int status = rr0 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
+        int status;
         int64_t it = 0;
-        while (status == VTX_CG_MAXITER && it < o.max_iter) {
-            if (sqrt(rr) <= o.tol * sqrt(rr0)) {
-                status = VTX_CONVERGED;
-                break;
-            }
-            for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
-                hvp_cell_one<PosT, M>(t, X, p, q, aux, c);
-            __syncthreads();
-            double d = 0.0;
-            for (int v = threadIdx.x; v < nv; v += blockDim.x)
-                d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, q, Aq, v);
-            const double pAp = bsum_bcast(d, sh, &s_bc);
-            if (!(pAp > 0.0)) {
-                status = VTX_CG_NEG_CURVATURE;
-                break;
-            }
-            const double al = rr / pAp;
-            double rn = 0.0;
+        double rel_res;
+        if (!o.minres) {
+            // CG: r = P b, q = r, x = 0
+            double rr = 0.0;
             for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-                const int64_t k = 2 * (int64_t)v;
-                x[k] += al * q[k];
-                x[k + 1] += al * q[k + 1];
-                const double r0 = r[k] - al * Aq[k], r1 = r[k + 1] - al * Aq[k + 1];
-                r[k] = r0;
-                r[k + 1] = r1;
-                rn += r0 * r0 + r1 * r1;
+                const double r0 = G.b[2 * (int64_t)v] - mbx, r1 = G.b[2 * (int64_t)v + 1] - mby;
+                r[2 * (int64_t)v] = r0;
+                r[2 * (int64_t)v + 1] = r1;
+                q[2 * (int64_t)v] = r0;
+                q[2 * (int64_t)v + 1] = r1;
+                x[2 * (int64_t)v] = 0.0;
+                x[2 * (int64_t)v + 1] = 0.0;
+                rr += r0 * r0 + r1 * r1;
             }
-            rn = bsum_bcast(rn, sh, &s_bc);
-            const double be = rn / rr;
-            rr = rn;
-            ++it;
+            rr = bsum_bcast(rr, sh, &s_bc);
+            const double rr0 = rr;
+            status = rr0 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
+            while (status == VTX_CG_MAXITER && it < o.max_iter) {
+                if (sqrt(rr) <= o.tol * sqrt(rr0)) {
+                    status = VTX_CONVERGED;
+                    break;
+                }
+                for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
+                    hvp_cell_one<PosT, M>(t, X, p, q, aux, c);
+                __syncthreads();
+                double d = 0.0;
+                for (int v = threadIdx.x; v < nv; v += blockDim.x)
+                    d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, q, Aq, v);
+                const double pAp = bsum_bcast(d, sh, &s_bc);
+                if (!(pAp > 0.0)) {
+                    status = VTX_CG_NEG_CURVATURE;
+                    break;
+                }
+                const double al = rr / pAp;
+                double rn = 0.0;
+                for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+                    const int64_t k = 2 * (int64_t)v;
+                    x[k] += al * q[k];
+                    x[k + 1] += al * q[k + 1];
+                    const double r0 = r[k] - al * Aq[k], r1 = r[k + 1] - al * Aq[k + 1];
+                    r[k] = r0;
+                    r[k + 1] = r1;
+                    rn += r0 * r0 + r1 * r1;
+                }
+                rn = bsum_bcast(rn, sh, &s_bc);
+                const double be = rn / rr;
+                rr = rn;
+                ++it;
+                for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+                    const int64_t k = 2 * (int64_t)v;
+                    q[k] = r[k] + be * q[k];
+                    q[k + 1] = r[k + 1] + be * q[k + 1];
+                }
+                __syncthreads();
+            }
+            if (status == VTX_CG_MAXITER && sqrt(rr) <= o.tol * sqrt(rr0)) status = VTX_CONVERGED;
+            rel_res = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+        } else {
+            // MINRES (the recurrences of k_mr_lanczos / k_mr_update): Lanczos
+            // vectors mq (current), mqp (previous), mz (next); search
+            // directions w1, w2; scalars are computed identically by every
+            // thread from block-wide sums.
+            double *mq = G.cg + 2 * (int64_t)nv, *mqp = G.cg + 4 * (int64_t)nv,
+                   *mz = G.cg + 6 * (int64_t)nv, *w1 = G.cg + 8 * (int64_t)nv,
+                   *w2 = G.cg + 10 * (int64_t)nv;
+            double ss = 0.0;
             for (int v = threadIdx.x; v < nv; v += blockDim.x) {
-                const int64_t k = 2 * (int64_t)v;
-                q[k] = r[k] + be * q[k];
-                q[k + 1] = r[k + 1] + be * q[k + 1];
+                const double r0 = G.b[2 * (int64_t)v] - mbx, r1 = G.b[2 * (int64_t)v + 1] - mby;
+                mq[2 * (int64_t)v] = r0;
+                mq[2 * (int64_t)v + 1] = r1;
+                ss += r0 * r0 + r1 * r1;
+            }
+            const double beta1 = sqrt(bsum_bcast(ss, sh, &s_bc));
+            const double inv1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+            for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
+                mq[k] *= inv1;
+                x[k] = mqp[k] = w1[k] = w2[k] = 0.0;
             }
             __syncthreads();
+            double beta = 0.0, c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0, phibar = beta1;
+            status = beta1 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
+            while (status == VTX_CG_MAXITER && it < o.max_iter) {
+                for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
+                    hvp_cell_one<PosT, M>(t, X, p, mq, aux, c);
+                __syncthreads();
+                double d = 0.0;
+                for (int v = threadIdx.x; v < nv; v += blockDim.x)
+                    d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, mq, mz, v);
+                const double alpha = bsum_bcast(d, sh, &s_bc);
+                double zz = 0.0;
+                for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
+                    const double zk = mz[k] - (alpha * mq[k] + beta * mqp[k]);
+                    mz[k] = zk;
+                    zz += zk * zk;
+                }
+                const double beta_next = sqrt(bsum_bcast(zz, sh, &s_bc));
+                const double eps = s2 * beta, dbar = c2 * beta;
+                const double delta = c1 * dbar + s1 * alpha;
+                const double gbar = -s1 * dbar + c1 * alpha;
+                const double gamma = sqrt(gbar * gbar + beta_next * beta_next);
+                ++it;
+                if (!(gamma > 0.0)) {
+                    status = fabs(phibar) <= o.tol * beta1 ? VTX_CONVERGED : VTX_CG_MAXITER;
+                    break;
+                }
+                const double c = gbar / gamma, s = beta_next / gamma;
+                const double tau = c * phibar;
+                phibar = -s * phibar;
+                for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
+                    const double qk = mq[k];
+                    const double w = (qk - delta * w1[k] - eps * w2[k]) / gamma;
+                    x[k] += tau * w;
+                    w2[k] = w1[k];
+                    w1[k] = w;
+                    mqp[k] = qk;
+                    mq[k] = beta_next > 0.0 ? mz[k] / beta_next : 0.0;
+                }
+                __syncthreads();
+                c2 = c1;
+                s2 = s1;
+                c1 = c;
+                s1 = s;
+                beta = beta_next;
+                if (fabs(phibar) <= o.tol * beta1) status = VTX_CONVERGED;
+                else if (!(beta_next > 0.0)) break;
+            }
+            rel_res = beta1 > 0.0 ? fabs(phibar) / beta1 : 0.0;
         }
-        if (status == VTX_CG_MAXITER && sqrt(rr) <= o.tol * sqrt(rr0)) status = VTX_CONVERGED;
         // project the solution to zero mean
         sx = 0.0;
         sy = 0.0;
@@ -246,7 +322,7 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
         if (threadIdx.x == 0) {
             vtx_grad_result gr{};
             gr.cg_iters = it;
-            gr.cg_rel_res = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+            gr.cg_rel_res = rel_res;
             gr.status = status;
             res[idx] = gr;
         }
@@ -745,14 +821,14 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         g.g = dC_dtheta[i];
     }
     hipError_t e;
-    if (o->method == VTX_GRAD_ADJOINT) {
+    if (o->method == VTX_GRAD_ADJOINT || o->method == VTX_GRAD_ADJOINT_MINRES) {
         if (!dC_dX) return set_error(VTX_E_ARG, "the adjoint needs dC_dX");
         for (int i = 0; i < n; ++i)
             if (!dC_dX[i]) return set_error(VTX_E_ARG, "null dC_dX in batch");
         if (!(o->cg_tol > 0) || o->cg_max_iter < 1) return set_error(VTX_E_ARG, "bad CG options");
         e = hipMemcpyAsync(b->gitems, items.data(), sizeof(GradItem) * n, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e);
-        GradOpts go{o->cg_tol, o->cg_max_iter, o->theta};
+        GradOpts go{o->cg_tol, o->cg_max_iter, o->theta, o->method == VTX_GRAD_ADJOINT_MINRES};
         const GradItem *gi = (const GradItem *)b->gitems;
         int rc = run_graph(b, s, [&](hipStream_t cs) {
             const dim3 grid(n), block(block_threads);

@@ -480,19 +480,21 @@ def small_equilibria(oracle):
     return out
 
 
+@pytest.mark.parametrize("solver", ["cg", "minres"])
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
-def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, theta):
+def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, theta, solver):
+    method = "adjoint" if solver == "cg" else "adjoint_minres"
     Ts, Xs, Ps, bs, refs = [], [], [], [], []
     for t, m, X, p, Xt in small_equilibria:
         T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
         _, b = oracle.v2v(m, X, Xt)
-        go, _ = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10)
+        go, _ = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10, solver=solver)
         gs, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=_dev(b), theta=theta,
-                             cg_tol=1e-10)
+                             cg_tol=1e-10, method=method)
         Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); bs.append(_dev(b))
         refs.append((go, gs.cpu().numpy()))
     B = vtx.Batch(Ts)
-    outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10)
+    outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10, method=method)
     for (go, gsingle), gb, inf in zip(refs, outs, infos):
         assert inf["status"] == 0
         gb = gb.cpu().numpy()
