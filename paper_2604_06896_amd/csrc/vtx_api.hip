@@ -60,7 +60,7 @@ ParamsRaw raw(const vtx_params *p) {
 // Host copy of the staged layouts.
 struct Staged {
     std::vector<int32_t> he_edge, edge_he, row_ptr, row_cap, corner, corner_he, nsides, cell_he;
-    std::vector<int32_t> star_nb, star_cell, star_edge, star_he;
+    std::vector<int32_t> star, star_he;
 };
 
 int validate_and_stage(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n_cell,
@@ -163,9 +163,7 @@ int validate_and_stage(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t 
         if (out_he[v] < 0) out_he[v] = (int32_t)h;
         ++out_n[v];
     }
-    S.star_nb.assign(3 * n_vert, 0);
-    S.star_cell.assign(3 * n_vert, 0);
-    S.star_edge.assign(3 * n_vert, 0);
+    S.star.assign(9 * n_vert, 0);
     S.star_he.assign(3 * n_vert, 0);
     for (int64_t v = 0; v < n_vert; ++v) {
         if (out_n[v] != 3)
@@ -176,9 +174,9 @@ int validate_and_stage(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t 
             if (R(h, HS) != v)
                 return fail(VTX_E_TOPOLOGY, "vertex %lld: star does not close", (long long)v);
             S.star_he[k * n_vert + v] = (int32_t)h;
-            S.star_nb[k * n_vert + v] = pack_id(R(h, HG), R(h, HOX), R(h, HOY));
-            S.star_cell[k * n_vert + v] = R(h, HF);
-            S.star_edge[k * n_vert + v] = S.he_edge[h];
+            S.star[star_nb_at(n_vert, k, v)] = pack_id(R(h, HG), R(h, HOX), R(h, HOY));
+            S.star[star_cell_at(n_vert, k, v)] = R(h, HF);
+            S.star[star_edge_at(n_vert, k, v)] = S.he_edge[h];
             h = R(R(h, HP), HT);
         }
         if (h != out_he[v])
@@ -204,7 +202,7 @@ void free_tissue(vtx_tissue t) {
     DevTissue &d = t->d;
     void *ptrs[] = {d.he, d.he_edge, d.edge_he, d.row_ptr, d.row_cap, d.pool_top, d.corner,
                     d.corner_he, d.nsides,
-                    d.cell_he, d.star_nb, d.star_cell, d.star_edge, d.star_he, t->w.xbuf,
+                    d.cell_he, d.star, d.star_he, t->w.xbuf,
                     t->w.cap, t->w.cell_aux, t->w.partials, t->w.partials2, t->w.mpart,
                     t->w.t1_list,
                     t->w.ctl, t->w.cg, t->w.scal, t->ep_buf};
@@ -393,9 +391,7 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
     UP(d.corner_he, S.corner_he);
     UP(d.nsides, S.nsides);
     UP(d.cell_he, S.cell_he);
-    UP(d.star_nb, S.star_nb);
-    UP(d.star_cell, S.star_cell);
-    UP(d.star_edge, S.star_edge);
+    UP(d.star, S.star);
     UP(d.star_he, S.star_he);
 #undef UP
     int64_t t1cap = 1;
@@ -474,8 +470,7 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he) {
         (rc = upload_into(d.pool_top, std::vector<int32_t>{d.pool_start})) ||
         (rc = upload_into(d.corner, S.corner)) || (rc = upload_into(d.corner_he, S.corner_he)) ||
         (rc = upload_into(d.nsides, S.nsides)) || (rc = upload_into(d.cell_he, S.cell_he)) ||
-        (rc = upload_into(d.star_nb, S.star_nb)) || (rc = upload_into(d.star_cell, S.star_cell)) ||
-        (rc = upload_into(d.star_edge, S.star_edge)) || (rc = upload_into(d.star_he, S.star_he)))
+        (rc = upload_into(d.star, S.star)) || (rc = upload_into(d.star_he, S.star_he)))
         return rc;
     return VTX_OK;
 }

@@ -85,9 +85,9 @@ struct Star {
     int nb[3];
 };
 
-// A star is loaded in three stages: (1) the coalesced star entries and the
-// own position, (2) every gather they index, issued before any is used,
-// (3) the arithmetic.
+// A star is loaded in three stages: (1) the star entries (two 16-byte and
+// one 4-byte coalesced load) and the own position, (2) every gather they
+// index, issued before any is used, (3) the arithmetic.
 template <typename PosT, typename M>
 struct StarLoad {
     int32_t w[3], c[3], e[3];
@@ -100,12 +100,17 @@ template <typename PosT, typename M>
 __device__ __forceinline__ void star_ids(const DevTissue &t, const PosT *__restrict__ X, int v,
                                          StarLoad<PosT, M> &L) {
     const int nv = t.n_vert;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        L.w[k] = t.star_nb[k * nv + v];
-        L.c[k] = t.star_cell[k * nv + v];
-        L.e[k] = t.star_edge[k * nv + v];
-    }
+    const int4 a = reinterpret_cast<const int4 *>(t.star)[v];
+    const int4 b = reinterpret_cast<const int4 *>(t.star + 4 * (int64_t)nv)[v];
+    L.e[2] = t.star[8 * (int64_t)nv + v];
+    L.w[0] = a.x;
+    L.w[1] = a.y;
+    L.w[2] = a.z;
+    L.c[0] = a.w;
+    L.c[1] = b.x;
+    L.c[2] = b.y;
+    L.e[0] = b.z;
+    L.e[1] = b.w;
     L.pi = ld2(X, v);
 }
 
@@ -225,9 +230,9 @@ __device__ __forceinline__ void star_refresh(const DevTissue &t, int v, int h0) 
     for (int k = 0; k < 3; ++k) {
         const int32_t *r = t.he + 8 * (int64_t)h;
         t.star_he[k * nv + v] = h;
-        t.star_nb[k * nv + v] = pack_id(r[HG], r[HOX], r[HOY]);
-        t.star_cell[k * nv + v] = r[HF];
-        t.star_edge[k * nv + v] = t.he_edge[h];
+        t.star[star_nb_at(nv, k, v)] = pack_id(r[HG], r[HOX], r[HOY]);
+        t.star[star_cell_at(nv, k, v)] = r[HF];
+        t.star[star_edge_at(nv, k, v)] = t.he_edge[h];
         h = t.he[8 * (int64_t)t.he[8 * (int64_t)h + HP] + HT];  // twin(prev(h))
     }
 }
@@ -771,7 +776,7 @@ __device__ __forceinline__ double hvp_vertex_one(const DevTissue &t, const PosT 
     const int nv = t.n_vert;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const auto g = ld2(aux, t.star_cell[k * nv + i]);
+        const auto g = ld2(aux, t.star[star_cell_at(nv, k, i)]);
         G[k] = g.x;
         B[k] = g.y;
         const auto vj = ld2(v, s.nb[k]);

@@ -46,11 +46,24 @@ struct DevTissue {
     int32_t *corner_he;  // [n_he] half-edge leaving each corner
     int32_t *nsides;     // [n_cell]
     int32_t *cell_he;    // [n_cell] one half-edge of each cell
-    int32_t *star_nb;    // [3][n_vert] packed neighbour id + image
-    int32_t *star_cell;  // [3][n_vert] sector cell k lies between neighbours k and k+1
-    int32_t *star_edge;  // [3][n_vert]
+    // Vertex stars (3 counter-clockwise slots k per vertex): neighbour nb_k
+    // (packed id + image), sector cell c_k (between neighbours k and k+1) and
+    // edge e_k, packed so that the vertex pass reads them with three loads:
+    //   [0, 4n)   int4 per vertex {nb_0, nb_1, nb_2, c_0}
+    //   [4n, 8n)  int4 per vertex {c_1, c_2, e_0, e_1}
+    //   [8n, 9n)  e_2
+    // (see star_nb_at / star_cell_at / star_edge_at).
+    int32_t *star;
     int32_t *star_he;    // [3][n_vert] outgoing half-edges, counter-clockwise
 };
+
+__host__ __device__ inline int64_t star_nb_at(int64_t n, int k, int64_t v) { return 4 * v + k; }
+__host__ __device__ inline int64_t star_cell_at(int64_t n, int k, int64_t v) {
+    return k == 0 ? 4 * v + 3 : 4 * n + 4 * v + (k - 1);
+}
+__host__ __device__ inline int64_t star_edge_at(int64_t n, int k, int64_t v) {
+    return k < 2 ? 4 * n + 4 * v + 2 + k : 8 * n + v;
+}
 
 template <typename P>
 struct DevParams {

@@ -255,6 +255,23 @@ def periodic_voronoi(seeds: np.ndarray, Lx: float, Ly: float,
     he[new_id, HE_FACE] = owner
     he[new_id, HE_OX] = ox
     he[new_id, HE_OY] = oy
+    if sort:
+        # Edges along the vertex order too (by their lower vertex id), so
+        # that per-edge data of neighbouring vertices sits close together.
+        n_e = n_he // 2
+        emin = np.minimum(he[0::2, HE_SRC], he[0::2, HE_TGT])
+        emax = np.maximum(he[0::2, HE_SRC], he[0::2, HE_TGT])
+        eperm = np.lexsort((emax, emin))            # new edge k = old edge eperm[k]
+        erank = np.empty(n_e, np.int64)
+        erank[eperm] = np.arange(n_e)
+        hmap = np.empty(n_he, np.int64)             # old half-edge id -> new
+        hmap[0::2] = 2 * erank
+        hmap[1::2] = 2 * erank + 1
+        he2 = np.empty_like(he)
+        he2[hmap] = he
+        for col in (HE_PREV, HE_NEXT, HE_TWIN):
+            he2[:, col] = hmap[he2[:, col]]
+        he = he2
     return Tissue(he.astype(np.int32), Xv, float(Lx), float(Ly), seeds)
 
 
