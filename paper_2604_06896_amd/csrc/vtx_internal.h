@@ -16,6 +16,7 @@ constexpr uint32_t kIdMask = (1u << kIdBits) - 1u;
 constexpr int kBlock = 256;          // threads per block of the grid kernels
 constexpr int kT1SortCap = 4096;     // T1 candidates sorted in LDS
 constexpr int kT1Extra = 256;        // pending re-checks during one T1 pass
+constexpr int kRedBlocks = 128;      // grid of the grid-stride reduction kernels
 constexpr int kRowSlack = 2;         // spare slots per row after a compaction
 constexpr int kRowExtra = 4;         // spare slots of a row moved to the pool
 
@@ -275,22 +276,25 @@ __device__ __forceinline__ double block_sum_array(const double *part, int n, int
     return block_sum(s, sh);
 }
 
-// Called by thread 0 after the block's results are stored (and after a
-// barrier, so the block's other stores have reached the cache): returns
-// true in exactly one block (the last to arrive), which then sees every
-// block's stores.  Arrivals only release; the acquire is taken once, by the
+// Called by thread 0 of each of n blocks after the block's results are
+// stored (and after a barrier, so the block's other stores have reached the
+// cache): returns true in exactly one of them (the last to arrive), which
+// then sees every block's stores.  Arrivals only release; the acquire is taken once, by the
 // last block.  On this multi-XCD part a device-scope release writes back the
 // XCD's L2 and an acquire invalidates it, so each costs tens of ns.  The
 // counter is reset by the last block.
-__device__ __forceinline__ bool last_block(unsigned int *counter) {
+__device__ __forceinline__ bool last_of(unsigned int *counter, unsigned int n) {
     const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-    const bool last = prev == gridDim.x - 1;
+    const bool last = prev == n - 1;
     if (last) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return last;
+}
+__device__ __forceinline__ bool last_block(unsigned int *counter) {
+    return last_of(counter, gridDim.x);
 }
 
 }  // namespace vtx

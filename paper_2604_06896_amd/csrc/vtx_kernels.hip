@@ -61,10 +61,12 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
         const double s = block_sum(e, sh);
         if (threadIdx.x == 0) epart[blockIdx.x] = s;
     }
-    if (flags & F_NUDGE_V2V) {
-        // mean over vertices of the v2v displacement (minimum image)
+    // mean over vertices of the v2v displacement (minimum image), by the
+    // first kRedBlocks blocks only (fewer device-scope arrivals)
+    const int nred = min((int)gridDim.x, kRedBlocks);
+    if ((flags & F_NUDGE_V2V) && (int)blockIdx.x < nred) {
         double sx = 0.0, sy = 0.0;
-        for (int v = blockIdx.x * kBlock + threadIdx.x; v < t.n_vert; v += gridDim.x * kBlock) {
+        for (int v = blockIdx.x * kBlock + threadIdx.x; v < t.n_vert; v += nred * kBlock) {
             sx += min_image((double)X[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
             sy += min_image((double)X[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
         }
@@ -74,12 +76,12 @@ __global__ __launch_bounds__(kBlock) void k_cell(DevTissue t, const PosT *__rest
         if (threadIdx.x == 0) {
             npart[2 * blockIdx.x] = bx;
             npart[2 * blockIdx.x + 1] = by;
-            s_last = last_block(&ctl->arrive2);
+            s_last = last_of(&ctl->arrive2, (unsigned)nred);
         }
         __syncthreads();
         if (s_last) {
-            const double ax = block_sum_array(npart, gridDim.x, 2, sh);
-            const double ay = block_sum_array(npart + 1, gridDim.x, 2, sh);
+            const double ax = block_sum_array(npart, nred, 2, sh);
+            const double ay = block_sum_array(npart + 1, nred, 2, sh);
             if (threadIdx.x == 0) {
                 const double nv = (double)t.n_vert;
                 ctl->nudge_mean[0] = ax / nv / nv;
@@ -292,6 +294,63 @@ __global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<P
     }
 }
 
+// ------------------------------------------------------ scalar reductions
+// A Krylov step ends with a sum over all vertices followed by scalar work
+// (step lengths, rotations, stopping tests).  Each block stores its partial;
+// grids of up to kLastBlockMax blocks finish in the last block to arrive,
+// larger grids in a one-block k_fin launch (thousands of device-scope
+// arrivals would serialise).  The scalar work is a functor run once, by one
+// thread, on the total.
+
+template <class Fin>
+__device__ __forceinline__ void reduce_tail(double val, double *part, LoopCtl *ctl,
+                                            double *sh, Fin fin) {
+    const double bs = block_sum(val, sh);
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = bs;
+        s_last = gridDim.x <= (unsigned)kLastBlockMax ? last_block(&ctl->arrive) : 0;
+    }
+    __syncthreads();
+    if (s_last) {
+        const double tot = block_sum_array(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) fin(ctl, tot);
+    }
+}
+
+template <class Fin>
+__global__ __launch_bounds__(1024) void k_fin(const double *__restrict__ part, int n,
+                                              LoopCtl *ctl, Fin fin) {
+    if (ctl->done) return;
+    __shared__ double sh[1024 / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) fin(ctl, tot);
+}
+
+template <class Fin>
+static void launch_fin(unsigned grid, const double *part, LoopCtl *ctl, Fin fin, hipStream_t s) {
+    if (grid > (unsigned)kLastBlockMax)
+        hipLaunchKernelGGL((k_fin<Fin>), dim3(1), dim3(1024), 0, s, part, (int)grid, ctl, fin);
+}
+
+// q.Hq of the HVP: CG's step length (and its curvature check); MINRES's
+// Lanczos coefficient alpha.
+struct FinPAp {
+    __device__ void operator()(LoopCtl *ctl, double pAp) const {
+        ctl->pAp = pAp;
+        if (ctl->solver == 0) {  // CG: stop on non-positive curvature
+            if (!(pAp > 0.0)) {
+                ctl->done = 1;
+                ctl->status = VTX_CG_NEG_CURVATURE;
+            } else {
+                ctl->alpha = ctl->rr / pAp;
+            }
+        }
+    }
+};
+
 // -------------------------------------------------------------------- HVP
 template <typename PosT, typename M>
 __global__ __launch_bounds__(kBlock) void k_hvp_cell(DevTissue t, const PosT *__restrict__ X,
@@ -318,29 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_hvp_vertex(DevTissue t, const PosT *
     const int i = xcd_block() * kBlock + threadIdx.x;
     double dot = 0.0;
     if (i < t.n_vert) dot = hvp_vertex_one<PosT, M>(t, X, p, cap, aux, v, Hv, i);
-    if (dpart) {
-        const double bs = block_sum(dot, sh);
-        __shared__ int s_last;
-        if (threadIdx.x == 0) {
-            dpart[blockIdx.x] = bs;
-            s_last = ctl ? last_block(&ctl->arrive) : 0;
-        }
-        __syncthreads();
-        if (s_last) {
-            const double pAp = block_sum_array(dpart, gridDim.x, 1, sh);
-            if (threadIdx.x == 0) {
-                ctl->pAp = pAp;
-                if (ctl->solver == 0) {  // CG: stop on non-positive curvature
-                    if (!(pAp > 0.0)) {
-                        ctl->done = 1;
-                        ctl->status = VTX_CG_NEG_CURVATURE;
-                    } else {
-                        ctl->alpha = ctl->rr / pAp;
-                    }
-                }
-            }
-        }
-    }
+    if (dpart) reduce_tail(dot, dpart, ctl, sh, FinPAp{});
 }
 
 // --------------------------------------------------------------------- CG
@@ -383,6 +420,18 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(const double *__restrict__ 
     out[2 * (int64_t)v + 1] = a[2 * (int64_t)v + 1] - mean[1];
 }
 
+struct FinCgInit {
+    __device__ void operator()(LoopCtl *ctl, double s) const {
+        ctl->rr = s;
+        ctl->rr0 = s;
+        ctl->rel_res = s > 0.0 ? 1.0 : 0.0;
+        if (!(s > 0.0)) {
+            ctl->done = 1;
+            ctl->status = VTX_CONVERGED;
+        }
+    }
+};
+
 // r = b - mean(b), p = r, x = 0, rr = r . r
 __global__ __launch_bounds__(kBlock) void k_cg_init(const double *__restrict__ b, int nv,
                                                     const double *mean, double *__restrict__ x,
@@ -402,26 +451,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(const double *__restrict__ b
         x[2 * (int64_t)v + 1] = 0.0;
         rr = rx * rx + ry * ry;
     }
-    const double bs = block_sum(rr, sh);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = bs;
-        s_last = last_block(&ctl->arrive);
-    }
-    __syncthreads();
-    if (s_last) {
-        const double s = block_sum_array(part, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            ctl->rr = s;
-            ctl->rr0 = s;
-            ctl->rel_res = s > 0.0 ? 1.0 : 0.0;
-            if (!(s > 0.0)) {
-                ctl->done = 1;
-                ctl->status = VTX_CONVERGED;
-            }
+    reduce_tail(rr, part, ctl, sh, FinCgInit{});
+}
+
+struct FinCgUpdate {
+    __device__ void operator()(LoopCtl *ctl, double s) const {
+        ctl->beta_cg = s / ctl->rr;
+        ctl->rr = s;
+        ctl->cg_iter += 1;
+        ctl->rel_res = sqrt(s / ctl->rr0);
+        if (sqrt(s) <= ctl->tol * sqrt(ctl->rr0)) {
+            ctl->done = 1;
+            ctl->status = VTX_CONVERGED;
+        } else if (ctl->cg_iter >= ctl->max_iter) {
+            ctl->done = 1;
+            ctl->status = VTX_CG_MAXITER;
         }
     }
-}
+};
 
 // x += alpha q, r -= alpha Aq, then beta = r.r / rr and the stopping tests.
 __global__ __launch_bounds__(kBlock) void k_cg_update(double *__restrict__ x,
@@ -443,29 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *__restrict__ x,
         r[k + 1] = r1;
         rr = r0 * r0 + r1 * r1;
     }
-    const double bs = block_sum(rr, sh);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = bs;
-        s_last = last_block(&ctl->arrive);
-    }
-    __syncthreads();
-    if (s_last) {
-        const double s = block_sum_array(part, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            ctl->beta_cg = s / ctl->rr;
-            ctl->rr = s;
-            ctl->cg_iter += 1;
-            ctl->rel_res = sqrt(s / ctl->rr0);
-            if (sqrt(s) <= ctl->tol * sqrt(ctl->rr0)) {
-                ctl->done = 1;
-                ctl->status = VTX_CONVERGED;
-            } else if (ctl->cg_iter >= ctl->max_iter) {
-                ctl->done = 1;
-                ctl->status = VTX_CG_MAXITER;
-            }
-        }
-    }
+    reduce_tail(rr, part, ctl, sh, FinCgUpdate{});
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_dir(const double *__restrict__ r,
@@ -586,12 +611,11 @@ __global__ __launch_bounds__(kBlock) void k_v2v(DevTissue t, const PosT *X, cons
                                                 double *grad, double *part, LoopCtl *ctl,
                                                 double *C_out) {
     __shared__ double sh[kBlock / 64];
-    const int v = blockIdx.x * kBlock + threadIdx.x;
     double c = 0.0;
-    if (v < t.n_vert) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < t.n_vert; v += gridDim.x * kBlock) {
         const double dx = min_image((double)X[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
         const double dy = min_image((double)X[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
-        c = dx * dx + dy * dy;
+        c += dx * dx + dy * dy;
         if (grad) {
             grad[2 * (int64_t)v] = dx / (double)t.n_vert;
             grad[2 * (int64_t)v + 1] = dy / (double)t.n_vert;
@@ -617,11 +641,10 @@ template <typename PosT>
 __global__ __launch_bounds__(kBlock) void k_dot_pos(const PosT *g, const PosT *X, int nv,
                                                     double *part, LoopCtl *ctl, double *out) {
     __shared__ double sh[kBlock / 64];
-    const int v = blockIdx.x * kBlock + threadIdx.x;
     double c = 0.0;
-    if (v < nv)
-        c = (double)g[2 * (int64_t)v] * (double)X[2 * (int64_t)v] +
-            (double)g[2 * (int64_t)v + 1] * (double)X[2 * (int64_t)v + 1];
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < nv; v += gridDim.x * kBlock)
+        c += (double)g[2 * (int64_t)v] * (double)X[2 * (int64_t)v] +
+             (double)g[2 * (int64_t)v + 1] * (double)X[2 * (int64_t)v + 1];
     const double bs = block_sum(c, sh);
     __shared__ int s_last;
     if (threadIdx.x == 0) {
@@ -678,6 +701,67 @@ struct MinresVecs {
     double *x, *q, *qp, *z, *w1, *w2;
 };
 
+struct FinMrInit {
+    __device__ void operator()(LoopCtl *ctl, double s2) const {
+        const double b1 = sqrt(s2);
+        ctl->mr_beta1 = b1;
+        ctl->mr_phibar = b1;
+        ctl->mr_beta = 0.0;
+        ctl->mr_c1 = ctl->mr_c2 = 1.0;
+        ctl->mr_s1 = ctl->mr_s2 = 0.0;
+        ctl->mr_noop = 1;
+        ctl->rel_res = b1 > 0.0 ? 1.0 : 0.0;
+        if (!(b1 > 0.0)) {
+            ctl->done = 1;
+            ctl->status = VTX_CONVERGED;
+        }
+    }
+};
+
+// The new tridiagonal column (beta, alpha, beta_next) meets the two previous
+// rotations, then a new rotation removes beta_next; the residual recurrence
+// and the stopping tests follow.
+struct FinMrLanczos {
+    __device__ void operator()(LoopCtl *ctl, double s2) const {
+        const double alpha = ctl->pAp, beta = ctl->mr_beta;
+        const double beta_next = sqrt(s2);
+        const double eps = ctl->mr_s2 * beta;
+        const double dbar = ctl->mr_c2 * beta;
+        const double delta = ctl->mr_c1 * dbar + ctl->mr_s1 * alpha;
+        const double gbar = -ctl->mr_s1 * dbar + ctl->mr_c1 * alpha;
+        const double gamma = sqrt(gbar * gbar + beta_next * beta_next);
+        ctl->cg_iter += 1;
+        if (!(gamma > 0.0)) {  // singular tridiagonal: no further progress
+            ctl->mr_noop = 1;
+            ctl->done = 1;
+            ctl->status = ctl->rel_res <= ctl->tol ? VTX_CONVERGED : VTX_CG_MAXITER;
+            return;
+        }
+        const double c = gbar / gamma, s = beta_next / gamma;
+        ctl->mr_delta = delta;
+        ctl->mr_eps = eps;
+        ctl->mr_gamma = gamma;
+        ctl->mr_tau = c * ctl->mr_phibar;
+        ctl->mr_beta_next = beta_next;
+        ctl->mr_phibar = -s * ctl->mr_phibar;
+        ctl->mr_c2 = ctl->mr_c1;
+        ctl->mr_s2 = ctl->mr_s1;
+        ctl->mr_c1 = c;
+        ctl->mr_s1 = s;
+        ctl->mr_beta = beta_next;
+        ctl->mr_noop = 0;
+        const double rel = fabs(ctl->mr_phibar) / ctl->mr_beta1;
+        ctl->rel_res = rel;
+        if (rel <= ctl->tol) {
+            ctl->done = 1;
+            ctl->status = VTX_CONVERGED;
+        } else if (!(beta_next > 0.0) || ctl->cg_iter >= ctl->max_iter) {
+            ctl->done = 1;
+            ctl->status = VTX_CG_MAXITER;
+        }
+    }
+};
+
 // z = P b (b minus its mean) into q, |P b|^2 -> beta1 and the initial state.
 __global__ __launch_bounds__(kBlock) void k_mr_init(const double *__restrict__ b, int nv,
                                                     const double *mean, MinresVecs m,
@@ -692,30 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_mr_init(const double *__restrict__ b
         m.q[k + 1] = ry;
         ss = rx * rx + ry * ry;
     }
-    const double bs = block_sum(ss, sh);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = bs;
-        s_last = last_block(&ctl->arrive);
-    }
-    __syncthreads();
-    if (s_last) {
-        const double s2 = block_sum_array(part, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            const double b1 = sqrt(s2);
-            ctl->mr_beta1 = b1;
-            ctl->mr_phibar = b1;
-            ctl->mr_beta = 0.0;
-            ctl->mr_c1 = ctl->mr_c2 = 1.0;
-            ctl->mr_s1 = ctl->mr_s2 = 0.0;
-            ctl->mr_noop = 1;
-            ctl->rel_res = b1 > 0.0 ? 1.0 : 0.0;
-            if (!(b1 > 0.0)) {
-                ctl->done = 1;
-                ctl->status = VTX_CONVERGED;
-            }
-        }
-    }
+    reduce_tail(ss, part, ctl, sh, FinMrInit{});
 }
 
 // q /= beta1; x = qp = w1 = w2 = 0.
@@ -749,53 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_mr_lanczos(int nv, MinresVecs m,
             ss += zk * zk;
         }
     }
-    const double bs = block_sum(ss, sh);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = bs;
-        s_last = last_block(&ctl->arrive);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    const double s2 = block_sum_array(part, gridDim.x, 1, sh);
-    if (threadIdx.x != 0) return;
-    const double beta_next = sqrt(s2);
-    // the new tridiagonal column (beta, alpha, beta_next) meets the two
-    // previous rotations, then a new rotation removes beta_next
-    const double eps = ctl->mr_s2 * beta;
-    const double dbar = ctl->mr_c2 * beta;
-    const double delta = ctl->mr_c1 * dbar + ctl->mr_s1 * alpha;
-    const double gbar = -ctl->mr_s1 * dbar + ctl->mr_c1 * alpha;
-    const double gamma = sqrt(gbar * gbar + beta_next * beta_next);
-    ctl->cg_iter += 1;
-    if (!(gamma > 0.0)) {  // singular tridiagonal: no further progress
-        ctl->mr_noop = 1;
-        ctl->done = 1;
-        ctl->status = ctl->rel_res <= ctl->tol ? VTX_CONVERGED : VTX_CG_MAXITER;
-        return;
-    }
-    const double c = gbar / gamma, s = beta_next / gamma;
-    ctl->mr_delta = delta;
-    ctl->mr_eps = eps;
-    ctl->mr_gamma = gamma;
-    ctl->mr_tau = c * ctl->mr_phibar;
-    ctl->mr_beta_next = beta_next;
-    ctl->mr_phibar = -s * ctl->mr_phibar;
-    ctl->mr_c2 = ctl->mr_c1;
-    ctl->mr_s2 = ctl->mr_s1;
-    ctl->mr_c1 = c;
-    ctl->mr_s1 = s;
-    ctl->mr_beta = beta_next;
-    ctl->mr_noop = 0;
-    const double rel = fabs(ctl->mr_phibar) / ctl->mr_beta1;
-    ctl->rel_res = rel;
-    if (rel <= ctl->tol) {
-        ctl->done = 1;
-        ctl->status = VTX_CONVERGED;
-    } else if (!(beta_next > 0.0) || ctl->cg_iter >= ctl->max_iter) {
-        ctl->done = 1;
-        ctl->status = VTX_CG_MAXITER;
-    }
+    reduce_tail(ss, part, ctl, sh, FinMrLanczos{});
 }
 
 __global__ __launch_bounds__(kBlock) void k_mr_update(int nv, MinresVecs m, const LoopCtl *ctl) {
@@ -985,9 +1000,11 @@ static void hvp_impl(const DevTissue &t, const Workspace &w, const void *X, cons
     auto p = dev_params<PosT>(pr);
     hipLaunchKernelGGL((k_hvp_cell<PosT, M>), dim3(blocks_for(t.n_cell)), dim3(kBlock), 0, s, t,
                        (const PosT *)X, p, v, (M *)w.cell_aux, ctl);
-    hipLaunchKernelGGL((k_hvp_vertex<PosT, M>), dim3(blocks_for(t.n_vert)), dim3(kBlock), 0, s,
-                       t, (const PosT *)X, p, (const M *)w.cap, (const M *)w.cell_aux, v, Hv,
+    const unsigned gv = blocks_for(t.n_vert);
+    hipLaunchKernelGGL((k_hvp_vertex<PosT, M>), dim3(gv), dim3(kBlock), 0, s, t,
+                       (const PosT *)X, p, (const M *)w.cap, (const M *)w.cell_aux, v, Hv,
                        dpart, ctl);
+    if (dpart) launch_fin(gv, dpart, ctl, FinPAp{}, s);
 }
 
 void launch_hvp(const DevTissue &t, const Workspace &w, int mode, const void *X,
@@ -1001,11 +1018,12 @@ void launch_hvp(const DevTissue &t, const Workspace &w, int mode, const void *X,
 void launch_cg_init(const Workspace &w, int nv, const double *b, hipStream_t s) {
     double *x = w.cg, *r = w.cg + 2 * (int64_t)nv, *q = w.cg + 4 * (int64_t)nv;
     const unsigned gv = blocks_for(nv);
-    const unsigned gm = gv < 1024 ? gv : 1024;
+    const unsigned gm = gv < (unsigned)kRedBlocks ? gv : (unsigned)kRedBlocks;
     hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, b, nv, w.partials2, w.ctl,
                        w.scal);
     hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, b, nv, (const double *)w.scal,
                        x, r, q, w.partials, w.ctl);
+    launch_fin(gv, w.partials, w.ctl, FinCgInit{}, s);
 }
 
 void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void *X,
@@ -1017,6 +1035,7 @@ void launch_cg_iter(const DevTissue &t, const Workspace &w, int mode, const void
     const unsigned gv = blocks_for(nv);
     hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, x, r, (const double *)q,
                        (const double *)Aq, nv, w.partials, w.ctl);
+    launch_fin(gv, w.partials, w.ctl, FinCgUpdate{}, s);
     hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(kBlock), 0, s, (const double *)r, q, nv, w.ctl);
 }
 
@@ -1027,12 +1046,13 @@ static MinresVecs minres_vecs(const Workspace &w, int nv) {
 
 void launch_minres_init(const Workspace &w, int nv, const double *b, hipStream_t s) {
     const unsigned gv = blocks_for(nv);
-    const unsigned gm = gv < 1024 ? gv : 1024;
+    const unsigned gm = gv < (unsigned)kRedBlocks ? gv : (unsigned)kRedBlocks;
     const MinresVecs m = minres_vecs(w, nv);
     hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, b, nv, w.partials2, w.ctl,
                        w.scal);
     hipLaunchKernelGGL(k_mr_init, dim3(gv), dim3(kBlock), 0, s, b, nv, (const double *)w.scal,
                        m, w.partials, w.ctl);
+    launch_fin(gv, w.partials, w.ctl, FinMrInit{}, s);
     hipLaunchKernelGGL(k_mr_init2, dim3(gv), dim3(kBlock), 0, s, nv, m, (const LoopCtl *)w.ctl);
 }
 
@@ -1043,12 +1063,13 @@ void launch_minres_iter(const DevTissue &t, const Workspace &w, int mode, const 
     launch_hvp(t, w, mode, X, p, m.q, m.z, w.partials, w.ctl, s);
     const unsigned gv = blocks_for(nv);
     hipLaunchKernelGGL(k_mr_lanczos, dim3(gv), dim3(kBlock), 0, s, nv, m, w.partials, w.ctl);
+    launch_fin(gv, w.partials, w.ctl, FinMrLanczos{}, s);
     hipLaunchKernelGGL(k_mr_update, dim3(gv), dim3(kBlock), 0, s, nv, m, (const LoopCtl *)w.ctl);
 }
 
 void launch_project(const Workspace &w, int nv, double *x, hipStream_t s) {
     const unsigned gv = blocks_for(nv);
-    const unsigned gm = gv < 1024 ? gv : 1024;
+    const unsigned gm = gv < (unsigned)kRedBlocks ? gv : (unsigned)kRedBlocks;
     hipLaunchKernelGGL(k_mean2, dim3(gm), dim3(kBlock), 0, s, (const double *)x, nv, w.partials2,
                        w.ctl + 1, w.scal + 2);
     hipLaunchKernelGGL(k_sub_mean, dim3(gv), dim3(kBlock), 0, s, (const double *)x, x, nv,
@@ -1110,7 +1131,8 @@ void launch_cell_exact(const DevTissue &t, int mode, const void *X, double *A, d
 
 void launch_v2v(const DevTissue &t, const Workspace &w, int mode, const void *X, const void *Xt,
                 double *C, double *grad, hipStream_t s) {
-    const unsigned gv = blocks_for(t.n_vert);
+    const unsigned gv0 = blocks_for(t.n_vert);
+    const unsigned gv = gv0 < (unsigned)kRedBlocks ? gv0 : (unsigned)kRedBlocks;
     if (mode == VTX_F32)
         hipLaunchKernelGGL((k_v2v<float>), dim3(gv), dim3(kBlock), 0, s, t, (const float *)X,
                            (const float *)Xt, grad, w.partials2, w.ctl + 1, C);
@@ -1135,7 +1157,8 @@ void launch_sens_rhs(const DevTissue &t, const Workspace &w, const void *X, cons
 
 void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const void *X,
                     double *out, hipStream_t s) {
-    const unsigned gv = blocks_for(nv);
+    const unsigned gv0 = blocks_for(nv);
+    const unsigned gv = gv0 < (unsigned)kRedBlocks ? gv0 : (unsigned)kRedBlocks;
     if (mode == VTX_F32)
         hipLaunchKernelGGL((k_dot_pos<float>), dim3(gv), dim3(kBlock), 0, s, (const float *)g,
                            (const float *)X, nv, w.partials2, w.ctl + 1, out);
@@ -1147,7 +1170,7 @@ void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const v
 void launch_mean_pos(const Workspace &w, int mode, int nv, const void *a, double *mean_out,
                      hipStream_t s) {
     const unsigned gv = blocks_for(nv);
-    const unsigned gm = gv < 1024 ? gv : 1024;
+    const unsigned gm = gv < (unsigned)kRedBlocks ? gv : (unsigned)kRedBlocks;
     if (mode == VTX_F32)
         hipLaunchKernelGGL((k_mean_pos<float>), dim3(gm), dim3(kBlock), 0, s, (const float *)a, nv,
                            w.partials2, w.ctl + 1, mean_out);
