@@ -98,3 +98,19 @@ def test_logistic_fit_recovers_transition():
     frac = 1.0 / (1.0 + np.exp(-(p0 - 3.83) / 0.03))
     pc, w = fit_logistic(p0, frac)
     assert pc == pytest.approx(3.83, abs=1e-6) and w == pytest.approx(0.03, rel=1e-5)
+
+
+def test_empty_and_oversized_inputs_are_rejected(libvtx):
+    t = g.random_tissue(20, np.sqrt(20.0), seed=5)
+    # empty table
+    rc, msg = _create(libvtx, np.zeros((0, 8), np.int32), 0, 0)
+    assert rc == -1, msg
+    # odd half-edge count
+    rc, msg = _create(libvtx, t.he[:-1], t.n_vert, t.n_cell)
+    assert rc == -1, msg
+    # vertex ids are packed in 28 bits: larger tissues are refused up front
+    rc, msg = _create(libvtx, t.he, 1 << 28, t.n_cell)
+    assert rc == -3 and "2^28" in msg, msg
+    # a declared cell that no half-edge bounds
+    rc, msg = _create(libvtx, t.he, t.n_vert, t.n_cell + 1)
+    assert rc == -2, msg
