@@ -212,6 +212,46 @@ def test_relax_with_t1_to_equilibrium_f64(vtx, oracle):
     assert np.abs(Fo).max() < 1e-6
 
 
+def test_relax_10k_cells_full_size(vtx, oracle):
+    """The 10^4-cell workload (P0 ~ U[3.6, 3.9] per cell, lambda ~ N(0.1,
+    0.02^2), T1 below 0.01) at full size: the first 300 iterations in FP64
+    against the oracle (every T1 event of the initial passes, bit-exact
+    topology), then 2e4 MIXED iterations checked by properties: a valid
+    3-valent periodic tiling with the box area, and the reported energy
+    equal to the oracle's at the returned state."""
+    t, p = g.workload_single_10k()
+    P = vtx.Params.from_numpy(p)
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    ro = oracle.relax(m, X, p, eta=3e-3, tol=0.0, patience=1, max_iter=300, t1_enable=True,
+                      l_min=0.01)
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    r = T.relax(Xd, P, mode="f64", eta=3e-3, tol=0.0, max_iter=300, t1_enable=True, l_min=0.01)
+    print("10k cells, 300 f64 iterations:", r, ro)
+    assert ro["n_t1"] + ro["n_stretch"] > 100
+    assert (r["iters"], r["n_t1"], r["n_stretch"]) == (ro["iters"], ro["n_t1"], ro["n_stretch"])
+    np.testing.assert_array_equal(T.topology(), m.he)
+    assert np.abs(Xd.cpu().numpy() - X).max() < 1e-9
+    # MIXED, longer
+    T2 = vtx.Tissue.from_tissue(t)
+    Xm = _dev(t.X)
+    r2 = T2.relax(Xm, P, mode="mixed", eta=3e-3, tol=0.0, max_iter=20000, t1_enable=True,
+                  l_min=0.01)
+    he = T2.topology()
+    m2 = oracle.Mesh(he, t.n_vert, t.Lx, t.Ly)
+    Xh = Xm.cpu().numpy()
+    A, Pc, ns = oracle.cells(m2, Xh)
+    assert ns.sum() == he.shape[0] and np.bincount(he[:, 3], minlength=t.n_vert).min() == 3
+    assert np.bincount(he[:, 3], minlength=t.n_vert).max() == 3 and ns.min() >= 3
+    assert A.sum() == pytest.approx(t.Lx * t.Ly, rel=1e-12) and A.min() > 0
+    Eo, Fo = oracle.energy_forces(m2, Xh, p)
+    print("10k cells, 2e4 mixed iterations:", r2, "oracle E", Eo, "max|F|", np.abs(Fo).max())
+    # the reported energy is that of the returned state (its line term summed
+    # from FP32 lengths in MIXED mode)
+    assert r2["energy"] == pytest.approx(Eo, rel=1e-7)
+
+
 def test_relax_mixed_precision_reaches_tolerance(vtx, oracle):
     """10^3-cell tissue, FP32 force arithmetic on FP64 positions, T1 on."""
     t, p = g.workload_single_10k(n_cell=1000, seed=221)
