@@ -398,6 +398,36 @@ def test_ep_forward_gradient_f64(vtx, oracle, equilibrium):
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
 
 
+def test_inverse_workload_full_size_gradients(vtx, oracle):
+    """One tissue of the 64 x 1000-cell inverse workload at full size: target
+    and prediction relaxed on the GPU (FP64, T1), then the adjoint (CG, tol
+    1e-8) and a Sen-ID directional derivative against the oracle's at the
+    same state and topology."""
+    t, ps, pi = g.workload_inverse(n_tissue=1)[0]
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=2000000, t1_enable=True, l_min=0.01)
+    Tt = vtx.Tissue.from_tissue(t)
+    Xt = _dev(t.X)
+    assert Tt.relax(Xt, vtx.Params.from_numpy(ps), mode="f64", **opts)["status"] == 0
+    T = vtx.Tissue.from_tissue(t)
+    X = _dev(t.X)
+    P = vtx.Params.from_numpy(pi)
+    assert T.relax(X, P, mode="f64", **opts)["status"] == 0
+    _, b = T.v2v(X, Xt)
+    gg, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-8)
+    m = oracle.Mesh(T.topology(), t.n_vert, t.Lx, t.Ly)
+    Xh, bh = X.cpu().numpy(), b.cpu().numpy()
+    go, info_o = oracle.adjoint_grad(m, Xh, pi, bh, tol=1e-8)
+    print("1000 cells adjoint:", info, info_o)
+    assert info["status"] == 0 and info_o["status"] == 0
+    assert abs(info["cg_iters"] - info_o["iters"]) <= 0.05 * info_o["iters"]
+    assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=t.n_edge)
+    sv, _, _ = T.param_sens(X, P, _dev(d), b, cg_tol=1e-8)
+    so, _, _ = oracle.sens_derivative(m, Xh, pi, d, bh, tol=1e-8)
+    assert sv.item() == pytest.approx(so, rel=1e-6)
+
+
 # ------------------------------------------------------------------- batched
 
 def _batch_case(rng, n, P0):
