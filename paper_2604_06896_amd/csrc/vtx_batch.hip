@@ -356,6 +356,52 @@ __global__ __launch_bounds__(1024) void k_batch_ep(const GradItem *__restrict__ 
     }
 }
 
+// Loop counters of one tissue's relaxation, kept in LDS by thread 0 so that
+// no register holds them across the T1 call.
+struct RelaxState {
+    int64_t iter, count, n_t1, n_st;
+    double last_mf;
+    int status, result_buf, bad_t1, done, changed;
+};
+
+// One T1 pass of a batched tissue (block-wide): sort the candidate edges,
+// run the sequential pass in one wave, compact the rows if one moved to the
+// pool.  Not inlined, and it receives the tissue only by address: the pass
+// needs many registers, and a caller that kept its own copies of the tissue
+// and parameters live across the call would spill them inside the cell and
+// vertex loops.
+template <typename PosT, typename M>
+__device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int ncand,
+                                           double l_min, double l_new, int32_t *sort_buf,
+                                           int32_t *extra, int32_t *scan, RelaxState *st) {
+    const BatchItem &B = *Bp;
+    const DevTissue &t = B.t;
+    const DevParams<PosT> p = to_dev<PosT>(B.p);
+    int np2 = 1;
+    while (np2 < ncand) np2 <<= 1;
+    int32_t *arr = np2 <= kT1SortCap ? sort_buf : B.t1_list;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x)
+        arr[i] = i < ncand ? t.he_edge[t.corner_he[B.t1_list[i]]] : INT_MAX;
+    __syncthreads();
+    block_bitonic(arr, np2);
+    if (threadIdx.x < 64) {  // one wave runs the pass
+        T1Counts r = t1_sequential<PosT, M>(t, Xc, p, (M *)B.cap, arr, ncand, extra, l_min,
+                                            l_new);
+        if (threadIdx.x == 0) {
+            st->n_t1 += r.swaps;
+            st->n_st += r.stretches;
+            st->changed = r.relocated;
+            if (r.overflow) st->bad_t1 = r.overflow;
+        }
+    }
+    __syncthreads();
+    if (st->changed) {
+        const int bad = rebuild_rows_block(t, scan);
+        if (threadIdx.x == 0 && bad) st->bad_t1 = 2;
+    }
+    __syncthreads();
+}
+
 template <typename PosT, typename M>
 __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restrict__ items,
                                                       const int32_t *__restrict__ order, int n,
@@ -366,7 +412,8 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
     __shared__ int32_t scan[1024];
     __shared__ double sh[16];
     __shared__ unsigned int s_cnt;
-    __shared__ int s_item, s_done, s_changed, s_rbuf;
+    __shared__ int s_item;
+    __shared__ RelaxState st;
     __shared__ double s_mean[2];
     const M lmin2 = (M)(o.l_min * o.l_min * (1.0 + 1e-4));
     for (;;) {
@@ -377,17 +424,17 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
         if (slot >= n) return;
         const int idx = order[slot];
         const BatchItem &B = items[idx];
-        const DevTissue t = B.t;
+        const DevTissue &t = B.t;
         const DevParams<PosT> p = to_dev<PosT>(B.p);
-        PosT *bufs[2] = {(PosT *)B.X, (PosT *)B.xbuf};
         M *cap = (M *)B.cap;
         int cur = 0;
-        int64_t iter = 0, count = 0, n_t1 = 0, n_st = 0;
-        int status = VTX_NOT_CONVERGED, result_buf = 0;
-        int bad_t1 = 0;  // meaningful in thread 0
-        double last_mf = 0.0;
+        if (threadIdx.x == 0) st = RelaxState{0, 0, 0, 0, 0.0, VTX_NOT_CONVERGED, 0, 0, 0, 0};
         for (;;) {
-            PosT *Xc = bufs[cur], *Xn = bufs[cur ^ 1];
+            // buffer selector and threshold as wave-uniform values (scalar
+            // registers), so they need no vector register across the T1 call
+            const int cu = __builtin_amdgcn_readfirstlane(cur);
+            PosT *Xc = (PosT *)(cu ? B.xbuf : B.X), *Xn = (PosT *)(cu ? B.X : B.xbuf);
+            const PosT lmin2p = (PosT)first_lane_f64((double)(PosT)lmin2);
             if (threadIdx.x == 0) s_cnt = 0u;
             __syncthreads();
             // cell pass
@@ -396,38 +443,16 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
                 PosT A, P;  // in the position precision, as in the grid kernels
                 cell_geom<PosT, PosT>(
                     t, Xc, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P,
-                    o.t1_enable != 0, (PosT)lmin2, B.t1_list, &s_cnt);
+                    o.t1_enable != 0, lmin2p, B.t1_list, &s_cnt);
                 st2(cap, c, (M)((PosT)2 * p.ka(c) * (A - p.a0(c))),
                     (M)((PosT)2 * p.kp(c) * (P - p.p0(c))));
             }
             __syncthreads();
             // T1 pass
             const int ncand = (int)s_cnt;
-            if (ncand > 0) {
-                int np2 = 1;
-                while (np2 < ncand) np2 <<= 1;
-                int32_t *arr = np2 <= kT1SortCap ? sort_buf : B.t1_list;
-                for (int i = threadIdx.x; i < np2; i += blockDim.x)
-                    arr[i] = i < ncand ? t.he_edge[t.corner_he[B.t1_list[i]]] : INT_MAX;
-                __syncthreads();
-                block_bitonic(arr, np2);
-                if (threadIdx.x < 64) {  // one wave runs the pass
-                    T1Counts r = t1_sequential<PosT, M>(t, Xc, p, cap, arr, ncand, extra,
-                                                        o.l_min, o.l_new);
-                    if (threadIdx.x == 0) {
-                        n_t1 += r.swaps;
-                        n_st += r.stretches;
-                        s_changed = r.relocated;
-                        if (r.overflow) bad_t1 = r.overflow;
-                    }
-                }
-                __syncthreads();
-                if (s_changed) {
-                    const int bad = rebuild_rows_block(t, scan);
-                    if (threadIdx.x == 0 && bad) bad_t1 = 2;
-                }
-                __syncthreads();
-            }
+            if (ncand > 0)
+                batch_t1_pass<PosT, M>(&B, Xc, ncand, o.l_min, o.l_new, sort_buf, extra, scan,
+                                       &st);
             // mean of the nudge gradient over the vertices
             const double inv_n = 1.0 / (double)t.n_vert;
             double mx = 0.0, my = 0.0;
@@ -470,37 +495,34 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
             }
             const double m = block_max(mf, sh);
             if (threadIdx.x == 0) {
-                ++iter;
-                last_mf = m;
-                int done = 0;
-                if (bad_t1) {
-                    done = 1;
-                    status = VTX_E_CAPACITY;
-                    result_buf = cur;
+                st.iter += 1;
+                st.last_mf = m;
+                if (st.bad_t1) {
+                    st.done = 1;
+                    st.status = VTX_E_CAPACITY;
+                    st.result_buf = cur;
                 } else if (!(m <= 1.7976931348623157e308)) {
-                    done = 1;
-                    status = VTX_E_NONFINITE;
-                    result_buf = cur;
+                    st.done = 1;
+                    st.status = VTX_E_NONFINITE;
+                    st.result_buf = cur;
                 } else {
-                    count = m < o.tol ? count + 1 : 0;
-                    if (count >= o.patience) {
-                        done = 1;
-                        status = VTX_CONVERGED;
-                        result_buf = cur;
-                    } else if (iter >= o.max_iter) {
-                        done = 1;
-                        status = VTX_NOT_CONVERGED;
-                        result_buf = cur ^ 1;
+                    st.count = m < o.tol ? st.count + 1 : 0;
+                    if (st.count >= o.patience) {
+                        st.done = 1;
+                        st.status = VTX_CONVERGED;
+                        st.result_buf = cur;
+                    } else if (st.iter >= o.max_iter) {
+                        st.done = 1;
+                        st.status = VTX_NOT_CONVERGED;
+                        st.result_buf = cur ^ 1;
                     }
                 }
-                s_done = done;
-                s_rbuf = result_buf;
             }
             __syncthreads();
-            if (s_done) break;
+            if (st.done) break;
             cur ^= 1;
         }
-        const int rbuf = s_rbuf;
+        const int rbuf = st.result_buf;
         if (rbuf == 1)
             for (int k = threadIdx.x; k < 2 * t.n_vert; k += blockDim.x)
                 ((PosT *)B.X)[k] = ((PosT *)B.xbuf)[k];
@@ -538,12 +560,12 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
         const double E = block_sum(e, sh);
         if (threadIdx.x == 0) {
             vtx_relax_result r;
-            r.iters = iter;
-            r.n_t1 = n_t1;
-            r.n_stretch = n_st;
-            r.max_f = last_mf;
+            r.iters = st.iter;
+            r.n_t1 = st.n_t1;
+            r.n_stretch = st.n_st;
+            r.max_f = st.last_mf;
             r.energy = E;
-            r.status = status;
+            r.status = st.status;
             res[idx] = r;
         }
         __syncthreads();

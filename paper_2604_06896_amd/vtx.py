@@ -426,8 +426,10 @@ class Batch:
 
     def param_grad(self, Xs, params_list, dC_dX=None, X_target=None, method="adjoint",
                    theta="lambda", mode="f64", cg_tol=1e-8, cg_max_iter=100000, beta=1e-3,
-                   ep_relax=None, block_threads=256):
-        """Hypergradients of every tissue in one batched launch sequence."""
+                   ep_relax=None, block_threads=1024):
+        """Hypergradients of every tissue in one batched launch sequence
+        (one workgroup of `block_threads` per tissue; 1024 suits tissues of
+        ~10^3 cells, where each solve step is bound by load latency)."""
         m = _mode(mode)
         n = len(self.tissues)
         keep = []
