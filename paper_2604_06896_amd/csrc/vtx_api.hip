@@ -338,6 +338,7 @@ namespace vtx {
 const DevTissue &tissue_dev(vtx_tissue t) { return t->d; }
 const Workspace &tissue_ws(vtx_tissue t) { return t->w; }
 int64_t tissue_size(vtx_tissue t) { return t->n_vert; }
+int64_t tissue_cells(vtx_tissue t) { return t->n_cell; }
 double *tissue_ep_buf(vtx_tissue t) { return t->ep_buf; }
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 }  // namespace vtx

@@ -23,6 +23,7 @@ namespace vtx {
 const DevTissue &tissue_dev(vtx_tissue t);
 const Workspace &tissue_ws(vtx_tissue t);
 int64_t tissue_size(vtx_tissue t);
+int64_t tissue_cells(vtx_tissue t);
 double *tissue_ep_buf(vtx_tissue t);
 int set_error(int code, const char *msg);
 }  // namespace vtx
@@ -124,15 +125,29 @@ __device__ __forceinline__ double bsum_bcast(double v, double *sh, double *bc) {
     return out;
 }
 
+// LDS bytes the batched adjoint needs to hold, for one tissue, the arrays its
+// Hessian-vector product gathers: positions, the vector multiplied, and the
+// two per-cell coefficient pairs (cA, cP at X* and G, B of the vector).
+template <typename PosT, typename M>
+__host__ __device__ inline int64_t cg_lds_bytes(int64_t n_vert, int64_t n_cell) {
+    auto a16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    return a16(2 * n_vert * (int64_t)sizeof(PosT)) + a16(2 * n_vert * 8) +
+           2 * a16(2 * n_cell * (int64_t)sizeof(M));
+}
+
 // Batched adjoint: one workgroup per tissue runs conjugate gradients on
 // H mu = P b (P removes the per-component mean) with FP64 dots, then the
 // contraction with the mixed derivatives (Methods, "Implicit
-// differentiation (ID)"); same steps as the grid path.
+// differentiation (ID)"); same steps as the grid path.  A tissue whose
+// gathered arrays fit in the launch's dynamic LDS (`lds_bytes`) keeps them
+// there for the whole solve: each step's gathers then wait on LDS instead
+// of the L2.  The arithmetic is the same either way.
 template <typename PosT, typename M>
 __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ items,
                                                    const int32_t *__restrict__ order, int n,
                                                    unsigned int *queue, GradOpts o,
-                                                   vtx_grad_result *res) {
+                                                   vtx_grad_result *res, int lds_bytes) {
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
     __shared__ double sh[16];
     __shared__ double s_bc;
     __shared__ int s_item;
@@ -147,10 +162,22 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
         const DevTissue t = G.t;
         const DevParams<PosT> p = to_dev<PosT>(G.p);
         const PosT *X = (const PosT *)G.X;
-        M *cap = (M *)G.cap;
-        M *aux = (M *)G.aux;
         const int nv = t.n_vert;
-        double *x = G.cg, *r = G.cg + 2 * (int64_t)nv, *q = G.cg + 4 * (int64_t)nv,
+        const bool in_lds = cg_lds_bytes<PosT, M>(nv, t.n_cell) <= (int64_t)lds_bytes;
+        const int64_t o_q = (2 * (int64_t)nv * (int64_t)sizeof(PosT) + 15) & ~(int64_t)15;
+        const int64_t o_c = o_q + ((2 * (int64_t)nv * 8 + 15) & ~(int64_t)15);
+        const int64_t o_a = o_c + ((2 * (int64_t)t.n_cell * (int64_t)sizeof(M) + 15) & ~(int64_t)15);
+        // Xh: positions read by the Hessian-vector product; qh: the vector it
+        // multiplies (q of CG, the Lanczos vector of MINRES)
+        const PosT *Xh = in_lds ? (const PosT *)lds_dyn : X;
+        M *cap = in_lds ? (M *)(lds_dyn + o_c) : (M *)G.cap;
+        M *aux = in_lds ? (M *)(lds_dyn + o_a) : (M *)G.aux;
+        if (in_lds) {
+            PosT *Xl = (PosT *)lds_dyn;
+            for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) Xl[k] = X[k];
+        }
+        double *x = G.cg, *r = G.cg + 2 * (int64_t)nv,
+               *q = in_lds ? (double *)(lds_dyn + o_q) : G.cg + 4 * (int64_t)nv,
                *Aq = G.cg + 6 * (int64_t)nv;
         // cell coefficients at X*
         for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
@@ -194,11 +221,11 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
                     break;
                 }
                 for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
-                    hvp_cell_one<PosT, M>(t, X, p, q, aux, c);
+                    hvp_cell_one<PosT, M>(t, Xh, p, q, aux, c);
                 __syncthreads();
                 double d = 0.0;
                 for (int v = threadIdx.x; v < nv; v += blockDim.x)
-                    d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, q, Aq, v);
+                    d += hvp_vertex_one<PosT, M>(t, Xh, p, cap, aux, q, Aq, v);
                 const double pAp = bsum_bcast(d, sh, &s_bc);
                 if (!(pAp > 0.0)) {
                     status = VTX_CG_NEG_CURVATURE;
@@ -233,7 +260,7 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
             // vectors mq (current), mqp (previous), mz (next); search
             // directions w1, w2; scalars are computed identically by every
             // thread from block-wide sums.
-            double *mq = G.cg + 2 * (int64_t)nv, *mqp = G.cg + 4 * (int64_t)nv,
+            double *mq = in_lds ? q : G.cg + 2 * (int64_t)nv, *mqp = G.cg + 4 * (int64_t)nv,
                    *mz = G.cg + 6 * (int64_t)nv, *w1 = G.cg + 8 * (int64_t)nv,
                    *w2 = G.cg + 10 * (int64_t)nv;
             double ss = 0.0;
@@ -254,11 +281,11 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
             status = beta1 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
             while (status == VTX_CG_MAXITER && it < o.max_iter) {
                 for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x)
-                    hvp_cell_one<PosT, M>(t, X, p, mq, aux, c);
+                    hvp_cell_one<PosT, M>(t, Xh, p, mq, aux, c);
                 __syncthreads();
                 double d = 0.0;
                 for (int v = threadIdx.x; v < nv; v += blockDim.x)
-                    d += hvp_vertex_one<PosT, M>(t, X, p, cap, aux, mq, mz, v);
+                    d += hvp_vertex_one<PosT, M>(t, Xh, p, cap, aux, mq, mz, v);
                 const double alpha = bsum_bcast(d, sh, &s_bc);
                 double zz = 0.0;
                 for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
@@ -602,6 +629,35 @@ int run_graph(vtx_batch b, hipStream_t s, Launch launch) {
     return e == hipSuccess ? VTX_OK : hip_fail(e);
 }
 
+// Launch of the batched adjoint with the dynamic LDS the largest tissue that
+// fits needs (tissues beyond the device's per-workgroup LDS keep their
+// arrays in global memory).
+template <typename PosT, typename M>
+int launch_batch_cg(vtx_batch b, const GradItem *gi, int n, const GradOpts &go,
+                    int block_threads, hipStream_t s) {
+    int dev = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    const int64_t budget = (int64_t)lds_max - 1024;  // the kernel's static LDS stays below
+    int64_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t nb = cg_lds_bytes<PosT, M>(tissue_size(b->ts[i]), tissue_cells(b->ts[i]));
+        if (nb <= budget && nb > need) need = nb;
+    }
+    const int lds = (int)need;
+    if (lds > 0) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_cg<PosT, M>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return run_graph(b, s, [&](hipStream_t cs) {
+        hipLaunchKernelGGL((k_batch_cg<PosT, M>), dim3(n), dim3(block_threads), (size_t)lds, cs,
+                           gi, b->order_d, n, b->queue, go, b->gres_d, lds);
+    });
+}
+
 int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
                     const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
                     double beta, int block_threads, vtx_relax_result *res, hipStream_t s) {
@@ -852,18 +908,13 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         if (e != hipSuccess) return hip_fail(e);
         GradOpts go{o->cg_tol, o->cg_max_iter, o->theta, o->method == VTX_GRAD_ADJOINT_MINRES};
         const GradItem *gi = (const GradItem *)b->gitems;
-        int rc = run_graph(b, s, [&](hipStream_t cs) {
-            const dim3 grid(n), block(block_threads);
-            if (mode == VTX_F32)
-                hipLaunchKernelGGL((k_batch_cg<float, float>), grid, block, 0, cs, gi, b->order_d,
-                                   n, b->queue, go, b->gres_d);
-            else if (mode == VTX_F64)
-                hipLaunchKernelGGL((k_batch_cg<double, double>), grid, block, 0, cs, gi,
-                                   b->order_d, n, b->queue, go, b->gres_d);
-            else
-                hipLaunchKernelGGL((k_batch_cg<double, float>), grid, block, 0, cs, gi, b->order_d,
-                                   n, b->queue, go, b->gres_d);
-        });
+        int rc;
+        if (mode == VTX_F32)
+            rc = launch_batch_cg<float, float>(b, gi, n, go, block_threads, s);
+        else if (mode == VTX_F64)
+            rc = launch_batch_cg<double, double>(b, gi, n, go, block_threads, s);
+        else
+            rc = launch_batch_cg<double, float>(b, gi, n, go, block_threads, s);
         if (rc) return rc;
         e = hipMemcpyAsync(res, b->gres_d, sizeof(vtx_grad_result) * n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
