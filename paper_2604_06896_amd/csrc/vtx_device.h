@@ -258,7 +258,7 @@ __device__ __forceinline__ HeRec he_rec(const DevTissue &t, int h) {
 constexpr int kRowPre = 12;
 template <typename PosT>
 __device__ __noinline__ void row_geom(const DevTissue &t, const PosT *X, int c,
-                                         const PosOverride<PosT> &ov, int edit, int va, int vb,
+                                         const PosOverride<PosT> ov, int edit, int va, int vb,
                                          int sx, int sy, double &A, double &P) {
     const int rb = t.row_ptr[c], n = t.nsides[c];
     int32_t w[kRowPre];
@@ -528,18 +528,15 @@ __device__ __noinline__ T1Counts t1_sequential(const DevTissue &t, PosT *X, cons
         const int cq = q == 0 ? C1 : q == 1 ? C2 : q == 2 ? C3 : C4;
         double A = 0.0, P = 0.0, Eq = 0.0;
         if (lane < 4 || (lane < 8 && admissible)) {
-            if (lane < 4) {
-                row_geom<PosT>(t, X, cq, S, 0, -1, -1, 0, 0, A, P);
-            } else {
-                // exchange: C1 drops j, C2 drops i, C3 gains j before i,
-                // C4 gains i before j
-                const int ed = q < 2 ? 1 : 2;
-                const int va = (q == 0 || q == 3) ? j : i;
-                const int vb = q == 2 ? j : (q == 3 ? i : -1);
-                const int sx = q == 2 ? rh.ox : (q == 3 ? -rh.ox : 0);
-                const int sy = q == 2 ? rh.oy : (q == 3 ? -rh.oy : 0);
-                row_geom<PosT>(t, X, cq, T, ed, va, vb, sx, sy, A, P);
-            }
+            // stretch: no row edit.  Exchange: C1 drops j, C2 drops i, C3
+            // gains j before i, C4 gains i before j.  One call site for both.
+            const bool ex = lane >= 4;
+            const int ed = !ex ? 0 : (q < 2 ? 1 : 2);
+            const int va = !ex ? -1 : ((q == 0 || q == 3) ? j : i);
+            const int vb = !ex ? -1 : (q == 2 ? j : (q == 3 ? i : -1));
+            const int sx = !ex ? 0 : (q == 2 ? rh.ox : (q == 3 ? -rh.ox : 0));
+            const int sy = !ex ? 0 : (q == 2 ? rh.oy : (q == 3 ? -rh.oy : 0));
+            row_geom<PosT>(t, X, cq, ex ? T : S, ed, va, vb, sx, sy, A, P);
             Eq = cell_energy<PosT>(p, cq, A, P);
         }
         bool take_T = false;
@@ -564,7 +561,7 @@ __device__ __noinline__ T1Counts t1_sequential(const DevTissue &t, PosT *X, cons
                                ln2 * ov_len<PosT>(t, X, T, j, rn2.tgt, rn2.ox - rh.ox, rn2.oy - rh.oy);
             take_T = ET0 + ETe < ES + ESe;
         }
-        const PosOverride<PosT> &W = take_T ? T : S;
+        const PosOverride<PosT> W = take_T ? T : S;
         // the kept candidate's lanes write the new coefficients of C1..C4
         if ((take_T && lane >= 4 && lane < 8) || (!take_T && lane < 4)) {
             cap[2 * (int64_t)cq] = (M)(2.0 * (double)p.ka(cq) * (A - (double)p.a0(cq)));
