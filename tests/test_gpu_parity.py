@@ -572,6 +572,37 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, 
         assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
 
 
+def test_batch_adjoint_lds_and_global_paths(vtx):
+    """One batch holding a tissue whose Hessian-product arrays fit in the
+    workgroup's LDS and one that does not (2600 cells in FP64: positions,
+    vector and two cell-coefficient pairs take ~250 KB): both equal the
+    single-tissue solve."""
+    rng = np.random.default_rng(61)
+    s = np.sqrt(2.0 / (3.0 * np.sqrt(3.0)))  # unit-area hexagons
+    Ts, Xs, Ps, bs, singles = [], [], [], [], []
+    for nx, ny in [(12, 10), (52, 50)]:
+        t = g.hex_lattice(nx, ny, s)
+        need = 32 * t.n_vert + 32 * t.n_cell  # FP64 bytes of the four arrays
+        assert need < 64 * 1024 if nx == 12 else need > 160 * 1024
+        # the regular tiling with uniform tension is an equilibrium by
+        # symmetry, and a stable one below the hexagon's shape index 3.72
+        p = g.uniform_params(t, P0=3.7)
+        p.lam = np.full(t.n_edge, 0.1)
+        T = vtx.Tissue.from_tissue(t)
+        P = vtx.Params.from_numpy(p)
+        X = _dev(t.X)
+        _, _, maxf = T.energy_forces(X, P, mode="f64", want_maxf=True)
+        assert float(maxf) < 1e-9
+        b = T.v2v(X, X + _dev(rng.normal(0, 0.05, t.X.shape)))[1]
+        gs, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-10)
+        assert info["status"] == 0, info
+        Ts.append(T); Xs.append(X); Ps.append(P); bs.append(b); singles.append(gs.cpu().numpy())
+    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10)
+    for gsingle, gb, inf in zip(singles, outs, infos):
+        assert inf["status"] == 0, inf
+        assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-7 * np.abs(gsingle).max()
+
+
 @pytest.mark.parametrize("method", ["ep", "ep_forward"])
 def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method):
     beta = 0.04
