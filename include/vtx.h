@@ -320,12 +320,17 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
                        int32_t *block_threads, double *trial_ms, void *stream);
 
 /* Hypergradients of every tissue of the batch (see vtx_param_grad).
- * ADJOINT: one persistent launch, one workgroup per tissue running the
- * whole CG solve and the contraction.  EP_CENTRED: two batched nudged
- * relaxations (vtx_batch_relax with a per-tissue nudge) and one estimate
- * launch.  X_star, p, dC_dX, X_target and dC_dtheta are host arrays of n
- * entries (device pointers inside; dC_dX or X_target may be NULL as for
- * vtx_param_grad).  Results go to the host array res[n]; synchronises. */
+ * ADJOINT / ADJOINT_MINRES: one persistent launch, one workgroup of
+ * `block_threads` (256, 512 or 1024) per tissue running the whole Krylov
+ * solve and the contraction; a tissue whose positions, solve vector and
+ * per-cell coefficients fit in the device's per-workgroup LDS keeps them
+ * there (same arithmetic either way).  EP_CENTRED / EP_FORWARD: batched
+ * nudged relaxations (vtx_batch_relax with a per-tissue nudge, workgroups
+ * of `block_threads`) and one estimate launch.  X_star, p, dC_dX, X_target
+ * and dC_dtheta are host arrays of n entries (device pointers inside; dC_dX
+ * or X_target may be NULL as for vtx_param_grad).  Results go to the host
+ * array res[n]; synchronises.  Errors: VTX_E_ARG (null arrays, bad mode,
+ * theta, method, options or block_threads), VTX_E_HIP. */
 int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const vtx_params *p,
                          const double *const *dC_dX, const void *const *X_target,
                          const vtx_grad_opts *o, double *const *dC_dtheta, int32_t block_threads,

@@ -625,7 +625,7 @@ int vtx_param_grad(vtx_tissue t, int32_t mode, const void *X_star, const vtx_par
         launch_ep(t->d, mode, Xp, Xm, raw(p), o->theta, o->beta, dC_dtheta, s);
         if ((rc = check_launch("EP estimate"))) return rc;
         HIPCHK(hipStreamSynchronize(s));
-        r.status = std::max(r.ep_plus.status, r.ep_minus.status);
+        r.status = combine_status(r.ep_plus.status, r.ep_minus.status);
     } else {
         return fail(VTX_E_ARG, "unknown hypergradient method");
     }

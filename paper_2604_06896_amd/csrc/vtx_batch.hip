@@ -699,17 +699,22 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
+    // As vtx_relax: a failed tissue reports NOT_CONVERGED and the call
+    // returns the error of the first failed tissue, naming it.
+    int err = VTX_OK, first = -1;
     for (int i = 0; i < n; ++i) {
-        if (res[i].status == VTX_E_NONFINITE) {
+        if (res[i].status == VTX_E_NONFINITE || res[i].status == VTX_E_CAPACITY) {
+            if (first < 0) {
+                first = i;
+                err = res[i].status;
+            }
             res[i].status = VTX_NOT_CONVERGED;
-            return set_error(VTX_E_NONFINITE, "non-finite forces in a batched relaxation");
-        }
-        if (res[i].status == VTX_E_CAPACITY) {
-            res[i].status = VTX_NOT_CONVERGED;
-            return set_error(VTX_E_CAPACITY, "T1 pass overflow in a batched relaxation");
         }
     }
-    return VTX_OK;
+    if (first < 0) return VTX_OK;
+    const std::string what = err == VTX_E_NONFINITE ? "non-finite forces" : "T1 pass overflow";
+    const std::string msg = what + " in batched relaxation of tissue " + std::to_string(first);
+    return set_error(err, msg.c_str());
 }
 
 int check_relax_opts(const vtx_relax_opts *o) {
@@ -970,7 +975,7 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         vtx_grad_result r{};
         r.ep_plus = rp[i];
         r.ep_minus = rm[i];
-        r.status = std::max(rp[i].status, rm[i].status);
+        r.status = combine_status(rp[i].status, rm[i].status);
         res[i] = r;
     }
     return VTX_OK;

@@ -20,6 +20,12 @@ constexpr int kRedBlocks = 128;      // grid of the grid-stride reduction kernel
 constexpr int kRowSlack = 2;         // spare slots per row after a compaction
 constexpr int kRowExtra = 4;         // spare slots of a row moved to the pool
 
+// Status of an estimate built from two relaxations: an error (negative)
+// wins, otherwise the worse of the two outcomes.
+__host__ __device__ inline int combine_status(int a, int b) {
+    return (a < 0 || b < 0) ? (a < b ? a : b) : (a > b ? a : b);
+}
+
 __host__ __device__ inline int32_t pack_id(int32_t id, int ox, int oy) {
     return (int32_t)((uint32_t)id | ((uint32_t)((ox + 1) | ((oy + 1) << 2)) << kIdBits));
 }

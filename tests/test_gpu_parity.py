@@ -622,6 +622,25 @@ def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method):
         assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-9 * np.abs(gsingle).max()
 
 
+@pytest.mark.parametrize("method", ["ep", "ep_forward"])
+def test_ep_status_reports_a_failed_relaxation(vtx, small_equilibria, method):
+    """A nudged relaxation that overflows (step 1e30) is reported as
+    VTX_E_NONFINITE, the error code of the single and of the batched call
+    (which names the first failed tissue), for centred and first-order EP."""
+    t, m, X, p, Xt = small_equilibria[0]
+    ep = dict(eta=1e30, tol=1e-12, max_iter=1000)
+    T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    P = vtx.Params.from_numpy(p)
+    with pytest.raises(vtx.VtxError) as err:
+        T.param_grad(_dev(X), P, X_target=_dev(Xt), method=method, beta=0.04, ep_relax=ep)
+    assert err.value.code == -5
+    T2 = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+    with pytest.raises(vtx.VtxError) as err:
+        vtx.Batch([T, T2]).param_grad([_dev(X), _dev(X)], [P, P], X_target=[_dev(Xt), _dev(Xt)],
+                                      method=method, beta=0.04, ep_relax=ep)
+    assert err.value.code == -5 and "tissue 0" in str(err.value)
+
+
 # ------------------------------------------------------------- autograd
 
 @pytest.mark.parametrize("method", ["adjoint", "ep"])
