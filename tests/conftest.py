@@ -1,3 +1,4 @@
+import json
 import os
 import sys
 
@@ -18,3 +19,22 @@ def oracle():
     import oracle as O
     O.build(force=False)
     return O
+
+
+# Measured errors of the GPU results against the oracle, by name; written as
+# JSON to the path in VTX_ERROR_REPORT when the session ends.
+_ERRORS = {}
+
+
+@pytest.fixture(scope="session")
+def errlog():
+    def record(name, value):
+        _ERRORS[name] = float(value)
+    return record
+
+
+def pytest_sessionfinish(session, exitstatus):
+    path = os.environ.get("VTX_ERROR_REPORT")
+    if path and _ERRORS:
+        with open(path, "w") as f:
+            json.dump(_ERRORS, f, indent=1, sort_keys=True)

@@ -42,7 +42,7 @@ def _force_err(F, Fo):
 # ----------------------------------------------------------- energy / forces
 
 @pytest.mark.parametrize("n_cell,seed", [(100, 101), (1000, 5), (37, 9)])
-def test_energy_forces_f64(vtx, oracle, n_cell, seed):
+def test_energy_forces_f64(vtx, oracle, errlog, n_cell, seed):
     rng = np.random.default_rng(seed)
     t = g.random_tissue(n_cell, np.sqrt(n_cell), rng=rng)
     p = _rand_params(t, rng)
@@ -51,13 +51,15 @@ def test_energy_forces_f64(vtx, oracle, n_cell, seed):
     T = vtx.Tissue.from_tissue(t)
     E, F, mf = T.energy_forces(_dev(X), vtx.Params.from_numpy(p), mode="f64", want_maxf=True)
     F = F.cpu().numpy()
+    errlog(f"forces f64, {n_cell} cells (max |dF| / max |F|)", _force_err(F, Fo))
+    errlog(f"energy f64, {n_cell} cells (relative)", abs(E.item() / Eo - 1))
     assert _force_err(F, Fo) < 1e-10
     assert E.item() == pytest.approx(Eo, rel=1e-12)
     assert mf.item() == pytest.approx(np.abs(Fo).max(), rel=1e-10)
 
 
 @pytest.mark.parametrize("mode", ["f32", "mixed"])
-def test_energy_forces_reduced_precision(vtx, oracle, mode):
+def test_energy_forces_reduced_precision(vtx, oracle, errlog, mode):
     t, p = g.workload_single_10k()
     dt = torch.float32 if mode == "f32" else torch.float64
     Xd = _dev(t.X, dt)
@@ -67,6 +69,8 @@ def test_energy_forces_reduced_precision(vtx, oracle, mode):
     E, F, _ = T.energy_forces(Xd, vtx.Params.from_numpy(p, dtype=dt), mode=mode)
     err = _force_err(F.double().cpu().numpy(), Fo)
     print(f"{mode}: max |dF| / max |F| = {err:.3e}, E rel err = {abs(E.item() / Eo - 1):.3e}")
+    errlog(f"forces {mode}, 1e4 cells (max |dF| / max |F|)", err)
+    errlog(f"energy {mode}, 1e4 cells (relative)", abs(E.item() / Eo - 1))
     assert err < 1e-5
     assert E.item() == pytest.approx(Eo, rel=1e-6)
 
@@ -94,7 +98,7 @@ def test_forces_deterministic(vtx):
     assert torch.equal(F1, F2) and E1.item() == E2.item()
 
 
-def test_force_kernel_full_size_1m_cells(vtx, oracle):
+def test_force_kernel_full_size_1m_cells(vtx, oracle, errlog):
     """The 10^6-cell workload in the launch configuration the benchmark times
     (FP32 positions); all 4e6 force components against the oracle."""
     t, p = g.workload_force_1m()
@@ -108,6 +112,8 @@ def test_force_kernel_full_size_1m_cells(vtx, oracle):
     Eo, Fo = oracle.energy_forces(oracle.Mesh.from_tissue(t), Xd.double().cpu().numpy(), pin)
     err = _force_err(F.double().cpu().numpy(), Fo)
     print(f"1e6 cells f32: max |dF| / max |F| = {err:.3e}")
+    errlog("forces f32, 1e6 cells (max |dF| / max |F|)", err)
+    errlog("energy f32, 1e6 cells (relative)", abs(E.item() / Eo - 1))
     assert err < 1e-5
     assert E.item() == pytest.approx(Eo, rel=1e-6)
 
@@ -128,7 +134,7 @@ def test_geometry_and_lengths(vtx, oracle):
 # ----------------------------------------------------------------------- T1
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
-def test_t1_pass_bit_exact_topology(vtx, oracle, mode):
+def test_t1_pass_bit_exact_topology(vtx, oracle, errlog, mode):
     t, p = g.workload_single_10k(n_cell=2000, seed=211)
     m = oracle.Mesh.from_tissue(t)
     X = t.X.copy()
@@ -140,6 +146,8 @@ def test_t1_pass_bit_exact_topology(vtx, oracle, mode):
     T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
     a, b = T.t1(Xd, vtx.Params.from_numpy(p), 0.01, 0.02, mode=mode)
     assert (a, b) == (n_sw, n_st)
+    errlog(f"T1 pass {mode}, 2000 cells: half-edge entries differing", (T.topology() != m.he).sum())
+    errlog(f"T1 pass {mode}, 2000 cells: positions (max abs)", np.abs(Xd.cpu().numpy() - X).max())
     np.testing.assert_array_equal(T.topology(), m.he)
     assert np.abs(Xd.cpu().numpy() - X).max() < 1e-12
     # the staged layouts follow: forces after the pass match the oracle
@@ -187,7 +195,7 @@ def test_relax_fixed_iterations_f64(vtx, oracle):
     assert r["energy"] == pytest.approx(ro["energy"], rel=1e-12)
 
 
-def test_relax_with_t1_to_equilibrium_f64(vtx, oracle):
+def test_relax_with_t1_to_equilibrium_f64(vtx, oracle, errlog):
     """100-cell tissue with T1 (l_min 0.01) relaxed to max |F| < 1e-6."""
     t, p = g.workload_single_100()
     m = oracle.Mesh.from_tissue(t)
@@ -206,13 +214,14 @@ def test_relax_with_t1_to_equilibrium_f64(vtx, oracle):
     ell = oracle.edge_lengths(m, X).mean()
     d = Xd.cpu().numpy() - X
     d -= t.Lx * np.round(d / t.Lx)
+    errlog("relaxed equilibrium f64, 100 cells with T1 (max |dX| / mean edge)", np.abs(d).max() / ell)
     assert np.abs(d).max() < 1e-4 * ell
     # the oracle confirms the returned state is an equilibrium
     _, Fo = oracle.energy_forces(m, Xd.cpu().numpy(), p)
     assert np.abs(Fo).max() < 1e-6
 
 
-def test_relax_10k_cells_full_size(vtx, oracle):
+def test_relax_10k_cells_full_size(vtx, oracle, errlog):
     """The 10^4-cell workload (P0 ~ U[3.6, 3.9] per cell, lambda ~ N(0.1,
     0.02^2), T1 below 0.01) at full size: the first 300 iterations in FP64
     against the oracle (every T1 event of the initial passes, bit-exact
@@ -232,6 +241,7 @@ def test_relax_10k_cells_full_size(vtx, oracle):
     assert ro["n_t1"] + ro["n_stretch"] > 100
     assert (r["iters"], r["n_t1"], r["n_stretch"]) == (ro["iters"], ro["n_t1"], ro["n_stretch"])
     np.testing.assert_array_equal(T.topology(), m.he)
+    errlog("1e4 cells, 300 f64 steps with T1: positions (max abs)", np.abs(Xd.cpu().numpy() - X).max())
     assert np.abs(Xd.cpu().numpy() - X).max() < 1e-9
     # MIXED, longer
     T2 = vtx.Tissue.from_tissue(t)
@@ -249,10 +259,12 @@ def test_relax_10k_cells_full_size(vtx, oracle):
     print("10k cells, 2e4 mixed iterations:", r2, "oracle E", Eo, "max|F|", np.abs(Fo).max())
     # the reported energy is that of the returned state (its line term summed
     # from FP32 lengths in MIXED mode)
+    errlog("1e4 cells, 2e4 mixed steps: reported energy vs FP64 energy of the state (relative)",
+           abs(r2["energy"] / Eo - 1))
     assert r2["energy"] == pytest.approx(Eo, rel=1e-7)
 
 
-def test_relax_mixed_precision_reaches_tolerance(vtx, oracle):
+def test_relax_mixed_precision_reaches_tolerance(vtx, oracle, errlog):
     """10^3-cell tissue, FP32 force arithmetic on FP64 positions, T1 on."""
     t, p = g.workload_single_10k(n_cell=1000, seed=221)
     T = vtx.Tissue.from_tissue(t)
@@ -263,6 +275,8 @@ def test_relax_mixed_precision_reaches_tolerance(vtx, oracle):
     assert r["status"] == 0
     m = oracle.Mesh(T.topology(), t.n_vert, t.Lx, t.Ly)
     _, Fo = oracle.energy_forces(m, Xd.cpu().numpy(), p)
+    errlog("mixed relaxation to 1e-6, 1000 cells: FP64 max |F| of the returned state",
+           np.abs(Fo).max())
     assert np.abs(Fo).max() < 2e-6          # FP64 forces of the FP32-relaxed state
 
 
@@ -283,18 +297,19 @@ def equilibrium(oracle):
     return t, m, X, p, Xt
 
 
-def test_hvp_f64(vtx, oracle, equilibrium):
+def test_hvp_f64(vtx, oracle, errlog, equilibrium):
     t, m, X, p, Xt = equilibrium
     rng = np.random.default_rng(3)
     v = rng.normal(size=X.shape)
     T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
     Hv = T.hvp(_dev(X), vtx.Params.from_numpy(p), _dev(v)).cpu().numpy()
     Hvo = oracle.hvp(m, X, p, v)
+    errlog("HVP f64 (max |d| / max)", np.abs(Hv - Hvo).max() / np.abs(Hvo).max())
     assert np.abs(Hv - Hvo).max() < 1e-10 * np.abs(Hvo).max()
 
 
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
-def test_adjoint_gradient_f64(vtx, oracle, equilibrium, theta):
+def test_adjoint_gradient_f64(vtx, oracle, errlog, equilibrium, theta):
     t, m, X, p, Xt = equilibrium
     _, b = oracle.v2v(m, X, Xt)
     go, info_o = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10)
@@ -303,11 +318,13 @@ def test_adjoint_gradient_f64(vtx, oracle, equilibrium, theta):
                             cg_tol=1e-10)
     assert info["status"] == 0
     assert abs(info["cg_iters"] - info_o["iters"]) <= 2
+    errlog(f"adjoint CG f64, theta={theta} (max |dg| / max |g|)",
+           np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max())
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-7 * np.abs(go).max()
 
 
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
-def test_adjoint_minres_f64(vtx, oracle, equilibrium, theta):
+def test_adjoint_minres_f64(vtx, oracle, errlog, equilibrium, theta):
     t, m, X, p, Xt = equilibrium
     _, b = oracle.v2v(m, X, Xt)
     go, info_o = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10, solver="minres")
@@ -317,6 +334,8 @@ def test_adjoint_minres_f64(vtx, oracle, equilibrium, theta):
     assert info["status"] == 0 and info_o["status"] == 0
     assert abs(info["cg_iters"] - info_o["iters"]) <= 2
     assert info["cg_rel_res"] <= 1e-10
+    errlog(f"adjoint MINRES f64, theta={theta} (max |dg| / max |g|)",
+           np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max())
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-7 * np.abs(go).max()
 
 
@@ -347,7 +366,7 @@ def test_minres_sensitivity_at_indefinite_state(vtx, oracle, seed):
     assert info_cg["status"] == vtx.CG_NEG_CURVATURE
 
 
-def test_ep_gradient_f64(vtx, oracle, equilibrium):
+def test_ep_gradient_f64(vtx, oracle, errlog, equilibrium):
     t, m, X, p, Xt = equilibrium
     beta = 0.04
     go, _ = oracle.ep_grad(m, X, p, Xt, beta, eta=3e-3, tol=1e-12, patience=1, max_iter=400000)
@@ -356,12 +375,14 @@ def test_ep_gradient_f64(vtx, oracle, equilibrium):
                             method="ep", beta=beta,
                             ep_relax=dict(eta=3e-3, tol=1e-12, max_iter=400000))
     assert info["status"] == 0
+    errlog("centred EP f64 vs the oracle's EP (max |dg| / max |g|)",
+           np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max())
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
 
 
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
-def test_sensitivity_f64(vtx, oracle, equilibrium, theta, mode):
+def test_sensitivity_f64(vtx, oracle, errlog, equilibrium, theta, mode):
     """Forward ID along a random direction: value and dX*/dtheta . d against
     the oracle, and against the library's own adjoint gradient . d."""
     t, m, X, p, Xt = equilibrium
@@ -379,13 +400,16 @@ def test_sensitivity_f64(vtx, oracle, equilibrium, theta, mode):
     tol = 1e-7 if mode == "f64" else 1e-3
     if mode == "f64":
         assert abs(info["cg_iters"] - info_o["iters"]) <= 2
+    errlog(f"Sen-ID {mode}, theta={theta}: derivative (relative)", abs(s.item() / so - 1))
+    errlog(f"Sen-ID {mode}, theta={theta}: dX*/dtheta.d (max |d| / max)",
+           np.abs(w.cpu().numpy() - wo).max() / np.abs(wo).max())
     assert s.item() == pytest.approx(so, rel=tol)
     assert np.abs(w.cpu().numpy() - wo).max() < tol * np.abs(wo).max()
     gg, _ = T.param_grad(_dev(X), P, dC_dX=_dev(b), theta=theta, cg_tol=1e-10)
     assert s.item() == pytest.approx(float(gg.cpu().numpy() @ d), rel=10 * tol)
 
 
-def test_ep_forward_gradient_f64(vtx, oracle, equilibrium):
+def test_ep_forward_gradient_f64(vtx, oracle, errlog, equilibrium):
     t, m, X, p, Xt = equilibrium
     beta = 0.04
     go, _ = oracle.ep_grad_forward(m, X, p, Xt, beta, eta=3e-3, tol=1e-12, patience=1,
@@ -395,10 +419,12 @@ def test_ep_forward_gradient_f64(vtx, oracle, equilibrium):
                             method="ep_forward", beta=beta,
                             ep_relax=dict(eta=3e-3, tol=1e-12, max_iter=400000))
     assert info["status"] == 0 and info["ep_minus"]["iters"] == 0
+    errlog("first-order EP f64 vs the oracle's (max |dg| / max |g|)",
+           np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max())
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
 
 
-def test_inverse_workload_full_size_gradients(vtx, oracle):
+def test_inverse_workload_full_size_gradients(vtx, oracle, errlog):
     """One tissue of the 64 x 1000-cell inverse workload at full size: target
     and prediction relaxed on the GPU (FP64, T1), then the adjoint (CG, tol
     1e-8) and a Sen-ID directional derivative against the oracle's at the
@@ -420,11 +446,14 @@ def test_inverse_workload_full_size_gradients(vtx, oracle):
     print("1000 cells adjoint:", info, info_o)
     assert info["status"] == 0 and info_o["status"] == 0
     assert abs(info["cg_iters"] - info_o["iters"]) <= 0.05 * info_o["iters"]
+    errlog("adjoint CG f64, 1000-cell inverse workload, tol 1e-8 (max |dg| / max |g|)",
+           np.abs(gg.cpu().numpy() - go).max() / np.abs(go).max())
     assert np.abs(gg.cpu().numpy() - go).max() < 1e-6 * np.abs(go).max()
     rng = np.random.default_rng(5)
     d = rng.normal(size=t.n_edge)
     sv, _, _ = T.param_sens(X, P, _dev(d), b, cg_tol=1e-8)
     so, _, _ = oracle.sens_derivative(m, Xh, pi, d, bh, tol=1e-8)
+    errlog("Sen-ID f64, 1000-cell inverse workload (relative)", abs(sv.item() / so - 1))
     assert sv.item() == pytest.approx(so, rel=1e-6)
 
 
@@ -438,7 +467,7 @@ def _batch_case(rng, n, P0):
 
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
-def test_batch_relax_matches_single(vtx, oracle, mode):
+def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
     """Solid tissues (P0 < 3.8; some converge within the iteration cap, some
     do not yet) plus one fluid tissue (P0 = 3.86) that keeps cycling short
     edges and stops at max_iter: the persistent batch kernel reproduces the
@@ -462,6 +491,8 @@ def test_batch_relax_matches_single(vtx, oracle, mode):
         assert r["status"] == rs["status"]
         assert (r["iters"], r["n_t1"], r["n_stretch"]) == (rs["iters"], rs["n_t1"], rs["n_stretch"])
         np.testing.assert_array_equal(T.topology(), he_ref)
+        errlog(f"batched vs single relaxation {mode}, {T.n_cell} cells: positions (max abs)",
+               np.abs(X.cpu().numpy() - Xs_ref).max())
         assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
         # the single path sums the line energy from FP32 lengths in MIXED mode
         assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9 if mode == "f64" else 1e-7)
@@ -552,7 +583,8 @@ def small_equilibria(oracle):
 
 @pytest.mark.parametrize("solver", ["cg", "minres"])
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
-def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, theta, solver):
+def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, errlog, small_equilibria, theta,
+                                                 solver):
     method = "adjoint" if solver == "cg" else "adjoint_minres"
     Ts, Xs, Ps, bs, refs = [], [], [], [], []
     for t, m, X, p, Xt in small_equilibria:
@@ -565,11 +597,14 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, small_equilibria, 
         refs.append((go, gs.cpu().numpy()))
     B = vtx.Batch(Ts)
     outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10, method=method)
+    worst = 0.0
     for (go, gsingle), gb, inf in zip(refs, outs, infos):
         assert inf["status"] == 0
         gb = gb.cpu().numpy()
+        worst = max(worst, np.abs(gb - go).max() / np.abs(go).max())
         assert np.abs(gb - gsingle).max() < 1e-9 * np.abs(go).max()
         assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
+    errlog(f"batched adjoint {solver} f64, theta={theta} (max |dg| / max |g|, worst tissue)", worst)
 
 
 def test_batch_adjoint_lds_and_global_paths(vtx):
