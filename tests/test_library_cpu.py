@@ -114,3 +114,20 @@ def test_empty_and_oversized_inputs_are_rejected(libvtx):
     # a declared cell that no half-edge bounds
     rc, msg = _create(libvtx, t.he, t.n_vert, t.n_cell + 1)
     assert rc == -2, msg
+
+
+def test_null_and_empty_arguments_are_rejected(libvtx):
+    """Argument checks that come before any device work."""
+    libvtx.vtx_last_error.restype = C.c_char_p
+    vp = C.c_void_p
+    libvtx.vtx_energy_forces.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    assert libvtx.vtx_energy_forces(None, 0, None, None, None, None, None, None) == -1
+    libvtx.vtx_relax.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
+    assert libvtx.vtx_relax(None, 0, None, None, None, None, None) == -1
+    libvtx.vtx_batch_create.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+    out = vp()
+    ts = (vp * 2)(None, None)
+    assert libvtx.vtx_batch_create(ts, 0, C.byref(out)) == -1       # empty batch
+    assert libvtx.vtx_batch_create(ts, 2, C.byref(out)) == -1       # null tissue
+    assert "null tissue" in libvtx.vtx_last_error().decode()
+    assert libvtx.vtx_batch_create(None, 2, C.byref(out)) == -1
