@@ -167,8 +167,9 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
         const int64_t o_q = (2 * (int64_t)nv * (int64_t)sizeof(PosT) + 15) & ~(int64_t)15;
         const int64_t o_c = o_q + ((2 * (int64_t)nv * 8 + 15) & ~(int64_t)15);
         const int64_t o_a = o_c + ((2 * (int64_t)t.n_cell * (int64_t)sizeof(M) + 15) & ~(int64_t)15);
-        // Xh: positions read by the Hessian-vector product; qh: the vector it
-        // multiplies (q of CG, the Lanczos vector of MINRES)
+        // LDS layout: positions (Xh, read by the Hessian-vector product), the
+        // vector it multiplies (q of CG, the Lanczos vector of MINRES), then
+        // the cell coefficients (cap) and the HVP's per-cell terms (aux)
         const PosT *Xh = in_lds ? (const PosT *)lds_dyn : X;
         M *cap = in_lds ? (M *)(lds_dyn + o_c) : (M *)G.cap;
         M *aux = in_lds ? (M *)(lds_dyn + o_a) : (M *)G.aux;
@@ -357,7 +358,10 @@ __global__ __launch_bounds__(1024) void k_batch_cg(const GradItem *__restrict__ 
     }
 }
 
-// Centred EP estimate from the two nudged states, one workgroup per tissue.
+// EP estimate from two states, one workgroup per tissue: the states nudged
+// by +beta/2 and -beta/2 (centred EP) or the state nudged by beta and X*
+// itself (first-order EP); either way the difference of the parameter
+// derivative of E divided by beta.
 template <typename PosT>
 __global__ __launch_bounds__(1024) void k_batch_ep(const GradItem *__restrict__ items, int n,
                                                    const void *const *Xm_list, double beta,
@@ -429,6 +433,15 @@ __device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int nc
     __syncthreads();
 }
 
+// Persistent batched relaxation (Methods, "Simulation engine", per tissue):
+// each workgroup takes tissues from a device queue (largest first) and runs
+// the whole gradient-descent loop of one tissue with workgroup barriers
+// only.  An iteration is the cell pass (coefficients, short-edge flags), the
+// T1 pass if any edge was flagged, the mean of the nudge gradient (EP), the
+// vertex pass with the step into the other position buffer, and the
+// convergence control; the arithmetic and the order of every step equal
+// those of the single-tissue kernels, so results are bit-identical to
+// vtx_relax.  The returned state is copied back into the caller's buffer.
 template <typename PosT, typename M>
 __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restrict__ items,
                                                       const int32_t *__restrict__ order, int n,
