@@ -142,7 +142,8 @@ def test_t1_pass_bit_exact_topology(vtx, oracle, errlog, mode):
     assert n_sw > 0 and n_st > 0
     T = vtx.Tissue.from_tissue(t)
     Xd = _dev(t.X)
-    # an evaluation before the pass builds the fused evaluation's tile tables
+    # an evaluation before the pass: the pass must see (and later replace)
+    # state left by earlier calls on the handle
     T.energy_forces(Xd, vtx.Params.from_numpy(p), mode="f64")
     a, b = T.t1(Xd, vtx.Params.from_numpy(p), 0.01, 0.02, mode=mode)
     assert (a, b) == (n_sw, n_st)
