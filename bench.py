@@ -86,7 +86,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library "
               "runs on a single MI355X and has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 

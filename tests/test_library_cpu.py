@@ -131,3 +131,14 @@ def test_null_and_empty_arguments_are_rejected(libvtx):
     assert libvtx.vtx_batch_create(ts, 2, C.byref(out)) == -1       # null tissue
     assert "null tissue" in libvtx.vtx_last_error().decode()
     assert libvtx.vtx_batch_create(None, 2, C.byref(out)) == -1
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU and says so for --gpus N > 1 (before any
+    device work)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
