@@ -132,6 +132,66 @@ def test_net_force_and_torque_free(oracle, small):
     assert np.abs(F.sum(0)).max() < 1e-11 * np.abs(F).max() * t.n_vert
 
 
+def test_single_cell_forces_are_torque_free(oracle, small):
+    """A cell's area and perimeter do not change under a rigid rotation of
+    its polygon, so the forces of one cell's term alone (every other cell's
+    K_A, K_P and every tension set to 0) act only on its corners and have
+    zero net force and zero torque about any point.  A missing rotation or a
+    wrong neighbour index in the pressure (area) term breaks this; the
+    overall sign of each term is pinned by the finite differences above."""
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    he = t.he
+    rng = np.random.default_rng(17)
+    for c in rng.choice(t.n_cell, 5, replace=False):
+        q = p.copy()
+        q.KA = np.where(np.arange(t.n_cell) == c, p.KA, 0.0)
+        q.KP = np.where(np.arange(t.n_cell) == c, p.KP, 0.0)
+        q.lam = np.zeros(t.n_edge)
+        _, F = oracle.energy_forces(m, t.X, q)
+        # the cell's corners, unwrapped relative to its first corner
+        h0 = int(np.flatnonzero(he[:, 5] == c)[0])
+        h, r, verts = h0, np.zeros(2), []
+        while True:
+            verts.append((int(he[h, 3]), r.copy()))
+            s_, g_ = he[h, 3], he[h, 4]
+            r = r + t.X[g_] + np.array([he[h, 6] * t.Lx, he[h, 7] * t.Ly]) - t.X[s_]
+            h = int(he[h, 1])
+            if h == h0:
+                break
+        idx = [v for v, _ in verts]
+        others = np.setdiff1d(np.arange(t.n_vert), idx)
+        scale = np.abs(F).max()
+        assert scale > 0 and np.abs(F[others]).max() == 0.0
+        Fc = np.array([F[v] for v in idx])
+        R = np.array([rv for _, rv in verts])
+        assert np.abs(Fc.sum(0)).max() < 1e-12 * scale
+        torque = np.sum(R[:, 0] * Fc[:, 1] - R[:, 1] * Fc[:, 0])
+        assert abs(torque) < 1e-12 * scale * np.abs(R).max() * len(idx)
+
+
+def test_single_edge_tension_is_central(oracle, small):
+    """A single line tension pulls its two end vertices towards each other
+    along the edge with force lambda: equal, opposite, parallel to it."""
+    t, p = small
+    m = oracle.Mesh.from_tissue(t)
+    q = p.copy()
+    q.KA = np.zeros(t.n_cell)
+    q.KP = np.zeros(t.n_cell)
+    e = 7
+    q.lam = np.where(np.arange(t.n_edge) == e, 0.3, 0.0)
+    _, F = oracle.energy_forces(m, t.X, q)
+    # the edge's half-edge: the lower id of the e-th twin pair
+    lower = sorted(int(k) for k in range(t.n_he) if k < t.he[k, 2])[e]
+    s_, g_ = t.he[lower, 3], t.he[lower, 4]
+    d = t.X[g_] + np.array([t.he[lower, 6] * t.Lx, t.he[lower, 7] * t.Ly]) - t.X[s_]
+    u = d / np.linalg.norm(d)
+    np.testing.assert_allclose(F[s_], 0.3 * u, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(F[g_], -0.3 * u, rtol=0, atol=1e-14)
+    others = np.setdiff1d(np.arange(t.n_vert), [s_, g_])
+    assert np.abs(F[others]).max() == 0.0
+
+
 def test_energy_decreases_along_force(oracle, small):
     t, p = small
     m = oracle.Mesh.from_tissue(t)
