@@ -222,6 +222,27 @@ def test_relax_with_t1_to_equilibrium_f64(vtx, oracle, errlog):
     assert np.abs(Fo).max() < 1e-6
 
 
+def test_relax_patience_and_stretch_length_f64(vtx, oracle):
+    """Patience 10 (the paper's benchmark setting) and a T1 length of
+    3 l_min instead of the default 2 l_min: iteration and event counts,
+    topology and positions as the oracle's."""
+    t, p = g.workload_single_100()
+    m = oracle.Mesh.from_tissue(t)
+    X = t.X.copy()
+    opts = dict(eta=1e-2, tol=1e-6, max_iter=200000, t1_enable=True, l_min=0.01, l_new=0.03)
+    ro = oracle.relax(m, X, p, patience=10, **opts)
+    assert ro["status"] == 0 and ro["n_t1"] + ro["n_stretch"] > 0
+    T = vtx.Tissue.from_tissue(t)
+    Xd = _dev(t.X)
+    r = T.relax(Xd, vtx.Params(P0=3.8, lam=0.0), mode="f64", patience=10, **opts)
+    assert (r["status"], r["iters"], r["n_t1"], r["n_stretch"]) == \
+        (ro["status"], ro["iters"], ro["n_t1"], ro["n_stretch"])
+    np.testing.assert_array_equal(T.topology(), m.he)
+    d = Xd.cpu().numpy() - X
+    d -= t.Lx * np.round(d / t.Lx)
+    assert np.abs(d).max() < 1e-4 * oracle.edge_lengths(m, X).mean()
+
+
 def test_relax_10k_cells_full_size(vtx, oracle, errlog):
     """The 10^4-cell workload (P0 ~ U[3.6, 3.9] per cell, lambda ~ N(0.1,
     0.02^2), T1 below 0.01) at full size: the first 300 iterations in FP64
