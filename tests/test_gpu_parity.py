@@ -488,7 +488,7 @@ def _batch_case(rng, n, P0):
     return t, p
 
 
-@pytest.mark.parametrize("mode", ["f64", "mixed"])
+@pytest.mark.parametrize("mode", ["f64", "mixed", "f32"])
 def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
     """Solid tissues (P0 < 3.8; some converge within the iteration cap, some
     do not yet) plus one fluid tissue (P0 = 3.86) that keeps cycling short
@@ -498,16 +498,17 @@ def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
     cases = [_batch_case(rng, n, P0) for n, P0 in
              ((64, 3.65), (150, 3.70), (90, 3.63), (300, 3.72), (120, 3.86))]
     opts = dict(eta=3e-3, tol=1e-6, max_iter=60000, t1_enable=True, l_min=0.01)
+    dt = vtx.pos_dtype(mode)
     single = []
     for t, p in cases:
         T = vtx.Tissue.from_tissue(t)
-        Xd = _dev(t.X)
-        r = T.relax(Xd, vtx.Params.from_numpy(p), mode=mode, **opts)
+        Xd = _dev(t.X, dt)
+        r = T.relax(Xd, vtx.Params.from_numpy(p, dtype=dt), mode=mode, **opts)
         single.append((r, Xd.cpu().numpy(), T.topology()))
     Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
-    Xs = [_dev(t.X) for t, _ in cases]
+    Xs = [_dev(t.X, dt) for t, _ in cases]
     B = vtx.Batch(Ts)
-    res = B.relax(Xs, [vtx.Params.from_numpy(p) for _, p in cases], mode=mode, **opts)
+    res = B.relax(Xs, [vtx.Params.from_numpy(p, dtype=dt) for _, p in cases], mode=mode, **opts)
     for (rs, Xs_ref, he_ref), r, X, T in zip(single, res, Xs, Ts):
         print("single", rs, "batch", r)
         assert r["status"] == rs["status"]
@@ -517,18 +518,20 @@ def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
                np.abs(X.cpu().numpy() - Xs_ref).max())
         assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
         # the single path sums the line energy from FP32 lengths in MIXED mode
-        assert r["energy"] == pytest.approx(rs["energy"], rel=1e-9 if mode == "f64" else 1e-7)
+        assert r["energy"] == pytest.approx(
+            rs["energy"], rel={"f64": 1e-9, "mixed": 1e-7, "f32": 1e-6}[mode])
     # evaluations after the batched T1 passes use the new topologies (at
     # perturbed positions: equilibrium forces are pure cancellation)
     for (t, p), X, T in zip(cases, Xs, Ts):
         m = oracle.Mesh.from_tissue(t)
         m.he[:] = T.topology()
-        Xh = X.cpu().numpy() + rng.normal(0, 0.02, t.X.shape)
+        Xh = X.double().cpu().numpy() + rng.normal(0, 0.02, t.X.shape)
         _, F, _ = T.energy_forces(_dev(Xh), vtx.Params.from_numpy(p), mode="f64")
         _, Fo = oracle.energy_forces(m, Xh, p)
         assert _force_err(F.cpu().numpy(), Fo) < 1e-10
     st = [r["status"] for r in res]
-    assert st[0] == 0 and st[2] == 0 and st[4] == 1
+    if mode != "f32":  # FP32 positions need not resolve a 1e-6 force tolerance
+        assert st[0] == 0 and st[2] == 0 and st[4] == 1
 
 
 def test_split_passes_equal_full_evaluation(vtx, oracle):
