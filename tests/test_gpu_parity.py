@@ -131,6 +131,62 @@ def test_geometry_and_lengths(vtx, oracle):
                                rtol=1e-12)
 
 
+def _many_sided_tissue():
+    """A seed inside a ring of 16 seeds (a 16-sided cell) among 260 random
+    seeds: 12 cells have more than 8 sides, one more than 12."""
+    rng = np.random.default_rng(3)
+    L = 20.0
+    c = np.array([L / 2, L / 2])
+    ang = np.linspace(0, 2 * np.pi, 16, endpoint=False) + 0.05
+    ring = c + np.stack([np.cos(ang), np.sin(ang)], 1)
+    far = []
+    while len(far) < 260:
+        q = rng.uniform(0, L, 2)
+        if np.linalg.norm(q - c) > 2.6:
+            far.append(q)
+    t = g.periodic_voronoi(np.vstack([c[None], ring, np.array(far)]), L, L)
+    return t, _rand_params(t, rng)
+
+
+def test_cells_with_many_sides(vtx, oracle):
+    """Corner loops past the prefetched slots (8 in the cell pass and the
+    HVP, 12 in the T1 row geometry): forces, geometry, HVP and a T1 pass
+    around the 16-sided cell as the oracle's."""
+    t, p = _many_sided_tissue()
+    ns = np.bincount(t.he[:, 5])
+    assert ns.max() == 16 and (ns > 8).sum() >= 10
+    m = oracle.Mesh.from_tissue(t)
+    T = vtx.Tissue.from_tissue(t)
+    P = vtx.Params.from_numpy(p)
+    Eo, Fo = oracle.energy_forces(m, t.X, p)
+    E, F, _ = T.energy_forces(_dev(t.X), P, mode="f64")
+    assert _force_err(F.cpu().numpy(), Fo) < 1e-10 and E.item() == pytest.approx(Eo, rel=1e-12)
+    E32, F32, _ = T.energy_forces(_dev(t.X, torch.float32), vtx.Params.from_numpy(
+        p, dtype=torch.float32), mode="f32")
+    Fo32 = oracle.energy_forces(m, _dev(t.X, torch.float32).double().cpu().numpy(), p)[1]
+    assert _force_err(F32.double().cpu().numpy(), Fo32) < 1e-5
+    A, Pc = T.cell_geometry(_dev(t.X))
+    Ao, Po, _ = oracle.cells(m, t.X)
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-12)
+    np.testing.assert_allclose(Pc.cpu().numpy(), Po, rtol=1e-12)
+    v = np.random.default_rng(4).normal(size=t.X.shape)
+    Hv = T.hvp(_dev(t.X), P, _dev(v)).cpu().numpy()
+    Hvo = oracle.hvp(m, t.X, p, v)
+    assert np.abs(Hv - Hvo).max() < 1e-10 * np.abs(Hvo).max()
+    # a T1 pass whose threshold makes half the 16-sided cell's edges short
+    big = int(np.argmax(ns))
+    ell = oracle.edge_lengths(m, t.X)
+    eoh, _ = oracle.edge_index(m)
+    l_min = float(np.median(ell[eoh[t.he[:, 5] == big]]))
+    X = t.X.copy()
+    n_sw, n_st = oracle.t1_pass(m, X, p, l_min, 1.2 * l_min)
+    assert n_sw + n_st > 0
+    Xd = _dev(t.X)
+    assert tuple(T.t1(Xd, P, l_min, 1.2 * l_min, mode="f64")) == (n_sw, n_st)
+    np.testing.assert_array_equal(T.topology(), m.he)
+    assert np.abs(Xd.cpu().numpy() - X).max() < 1e-12
+
+
 # ----------------------------------------------------------------------- T1
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
