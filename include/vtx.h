@@ -321,12 +321,16 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
 
 /* Hypergradients of every tissue of the batch (see vtx_param_grad).
  * ADJOINT / ADJOINT_MINRES: one persistent launch, one workgroup of
- * `block_threads` (256, 512 or 1024) per tissue running the whole Krylov
- * solve and the contraction; a tissue whose positions, solve vector and
- * per-cell coefficients fit in the device's per-workgroup LDS keeps them
- * there (same arithmetic either way).  EP_CENTRED / EP_FORWARD: batched
- * nudged relaxations (vtx_batch_relax with a per-tissue nudge, workgroups
- * of `block_threads`) and one estimate launch.  X_star, p, dC_dX, X_target
+ * `block_threads` (256, 512 or 1024; 0 chooses) per tissue running the
+ * whole Krylov solve and the contraction; a tissue whose positions, solve
+ * vector and per-cell coefficients fit in the device's per-workgroup LDS
+ * keeps them there, and with workgroups of at most 512 threads a CG solve of
+ * a tissue with at most two cells and four vertices per thread also keeps
+ * its corner rows in LDS and its stars, solution and residual in registers
+ * (same arithmetic in every form).  0 takes 512 threads when every tissue
+ * has that form, else 1024.  EP_CENTRED / EP_FORWARD: batched nudged
+ * relaxations (vtx_batch_relax with a per-tissue nudge, workgroups of
+ * `block_threads`, 0 meaning 1024) and one estimate launch.  X_star, p, dC_dX, X_target
  * and dC_dtheta are host arrays of n entries (device pointers inside; dC_dX
  * or X_target may be NULL as for vtx_param_grad).  Results go to the host
  * array res[n]; synchronises.  Errors: VTX_E_ARG (null arrays, bad mode,

@@ -703,19 +703,19 @@ __device__ __forceinline__ int rebuild_rows_block(const DevTissue &t, int32_t *s
 // precision of the positions:
 //   dA = sum_k grad_k A . v_k,  grad_k A = 1/2 R(r_{k+1} - r_{k-1});
 //   dP = sum_k u_k . (v_{k+1} - v_k)  (zero-length edges contribute 0).
-// Stored as (G, B) = (2 K_A dA, 2 K_P dP).
-template <typename PosT, typename M>
-__device__ __forceinline__ void hvp_cell_one(const DevTissue &t, const PosT *__restrict__ X,
-                                             const DevParams<PosT> &p,
-                                             const double *__restrict__ v, M *__restrict__ aux,
-                                             int c) {
+// Stored as (G, B) = (2 K_A dA, 2 K_P dP).  `corner_at(k)` returns the
+// packed corner k of the cell's row, which has n corners.
+template <typename PosT, typename M, typename CornerAt>
+__device__ __forceinline__ void hvp_cell_row(const DevTissue &t, const PosT *__restrict__ X,
+                                             const double *__restrict__ v, int n,
+                                             CornerAt corner_at, PosT ka, PosT kp,
+                                             M *__restrict__ aux, int c) {
     using C = PosT;
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
-    const int rb = t.row_ptr[c], n = t.nsides[c];
-    const int32_t w0 = t.corner[rb];
+    const int32_t w0 = corner_at(0);
     const auto p0 = ld2(X, id_of(w0));
     auto rel = [&](int k, C &rx, C &ry, C &vx, C &vy) {
-        const int32_t w = t.corner[rb + k];
+        const int32_t w = corner_at(k);
         const int vv = id_of(w);
         if (k == 0) {
             rx = 0;
@@ -750,30 +750,39 @@ __device__ __forceinline__ void hvp_cell_one(const DevTissue &t, const PosT *__r
         vcx = vnx;
         vcy = vny;
     }
-    st2(aux, c, (M)((C)2 * (C)p.ka(c) * dA), (M)((C)2 * (C)p.kp(c) * dP));
+    st2(aux, c, (M)((C)2 * (C)ka * dA), (M)((C)2 * (C)kp * dP));
+}
+
+template <typename PosT, typename M>
+__device__ __forceinline__ void hvp_cell_one(const DevTissue &t, const PosT *__restrict__ X,
+                                             const DevParams<PosT> &p,
+                                             const double *__restrict__ v, M *__restrict__ aux,
+                                             int c) {
+    const int rb = t.row_ptr[c], n = t.nsides[c];
+    hvp_cell_row<PosT, M>(
+        t, X, v, n, [&](int k) { return t.corner[rb + k]; }, p.ka(c), p.kp(c), aux, c);
 }
 
 // (H v)_i = sum_k [ T_k w_k - u_k (B_k + B_{k-1}) + 1/2 R(d_k)(G_k - G_{k-1})
 //                   + 1/2 R(v_{j_k} - v_i)(cA_k - cA_{k-1}) ]
 // with w_k = (I - u_k u_k^T)(v_i - v_{j_k}) / l_k, T_k the edge tension
 // (lambda_k + cP_k + cP_{k-1}), G = 2K_A dA and B = 2K_P dP of the sector
-// cells.  Writes (Hv)_i and returns v_i . (Hv)_i.
+// cells.  From a star whose entries and gathers are in `L`: returns
+// (Hv)_i in (hx, hy) and v_i . (Hv)_i.
 template <typename PosT, typename M>
-__device__ __forceinline__ double hvp_vertex_one(const DevTissue &t, const PosT *__restrict__ X,
-                                                 const DevParams<PosT> &p,
-                                                 const M *__restrict__ cap,
-                                                 const M *__restrict__ aux,
-                                                 const double *__restrict__ v,
-                                                 double *__restrict__ Hv, int i) {
+__device__ __forceinline__ double hvp_vertex_star(const DevTissue &t,
+                                                  const StarLoad<PosT, M> &L,
+                                                  const M *__restrict__ aux,
+                                                  const double *__restrict__ v, int i,
+                                                  double &hx_out, double &hy_out) {
     Star<PosT, M> s;
     PosT xi, yi;
-    load_star<PosT, M>(t, X, p, cap, i, s, xi, yi);
+    star_math<PosT, M>(t, L, s, xi, yi);
     const auto vi = ld2(v, i);
     M G[3], B[3], vx[3], vy[3];
-    const int nv = t.n_vert;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const auto g = ld2(aux, t.star[star_cell_at(nv, k, i)]);
+        const auto g = ld2(aux, L.c[k]);
         G[k] = g.x;
         B[k] = g.y;
         const auto vj = ld2(v, s.nb[k]);
@@ -794,8 +803,26 @@ __device__ __forceinline__ double hvp_vertex_one(const DevTissue &t, const PosT 
         hx += T * wx - s.ux[k] * Bs + dG * s.dy[k] + dC * vy[k];
         hy += T * wy - s.uy[k] * Bs - dG * s.dx[k] - dC * vx[k];
     }
-    st2(Hv, i, (double)hx, (double)hy);
+    hx_out = (double)hx;
+    hy_out = (double)hy;
     return vi.x * (double)hx + vi.y * (double)hy;
+}
+
+// Writes (Hv)_i and returns v_i . (Hv)_i.
+template <typename PosT, typename M>
+__device__ __forceinline__ double hvp_vertex_one(const DevTissue &t, const PosT *__restrict__ X,
+                                                 const DevParams<PosT> &p,
+                                                 const M *__restrict__ cap,
+                                                 const M *__restrict__ aux,
+                                                 const double *__restrict__ v,
+                                                 double *__restrict__ Hv, int i) {
+    StarLoad<PosT, M> L;
+    star_ids<PosT, M>(t, X, i, L);
+    star_gather<PosT, M>(X, p, cap, L);
+    double hx, hy;
+    const double d = hvp_vertex_star<PosT, M>(t, L, aux, v, i, hx, hy);
+    st2(Hv, i, hx, hy);
+    return d;
 }
 
 // ------------------------------------------------------------ contractions

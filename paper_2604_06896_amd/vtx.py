@@ -426,10 +426,12 @@ class Batch:
 
     def param_grad(self, Xs, params_list, dC_dX=None, X_target=None, method="adjoint",
                    theta="lambda", mode="f64", cg_tol=1e-8, cg_max_iter=100000, beta=1e-3,
-                   ep_relax=None, block_threads=1024):
+                   ep_relax=None, block_threads=0):
         """Hypergradients of every tissue in one batched launch sequence
-        (one workgroup of `block_threads` per tissue; 1024 suits tissues of
-        ~10^3 cells, where each solve step is bound by load latency)."""
+        (one workgroup of `block_threads` per tissue: 256, 512 or 1024, or 0
+        to let the library choose; for CG on tissues of up to 1024 cells it
+        takes 512 threads, which keep each solve's topology and vectors in
+        LDS and registers)."""
         m = _mode(mode)
         n = len(self.tissues)
         keep = []

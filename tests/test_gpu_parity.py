@@ -662,10 +662,13 @@ def small_equilibria(oracle):
     return out
 
 
+@pytest.mark.parametrize("block_threads", [1024, 512])
 @pytest.mark.parametrize("solver", ["cg", "minres"])
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
 def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, errlog, small_equilibria, theta,
-                                                 solver):
+                                                 solver, block_threads):
+    """Workgroups of 512 threads solve these tissues with CG in the
+    register-resident form, 1024-thread ones in the general loop."""
     method = "adjoint" if solver == "cg" else "adjoint_minres"
     Ts, Xs, Ps, bs, refs = [], [], [], [], []
     for t, m, X, p, Xt in small_equilibria:
@@ -677,7 +680,8 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, errlog, small_equi
         Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); bs.append(_dev(b))
         refs.append((go, gs.cpu().numpy()))
     B = vtx.Batch(Ts)
-    outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10, method=method)
+    outs, infos = B.param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10, method=method,
+                               block_threads=block_threads)
     worst = 0.0
     for (go, gsingle), gb, inf in zip(refs, outs, infos):
         assert inf["status"] == 0
@@ -685,21 +689,25 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, errlog, small_equi
         worst = max(worst, np.abs(gb - go).max() / np.abs(go).max())
         assert np.abs(gb - gsingle).max() < 1e-9 * np.abs(go).max()
         assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
-    errlog(f"batched adjoint {solver} f64, theta={theta} (max |dg| / max |g|, worst tissue)", worst)
+    errlog(f"batched adjoint {solver} f64, theta={theta}, {block_threads} threads "
+           "(max |dg| / max |g|, worst tissue)", worst)
 
 
-def test_batch_adjoint_lds_and_global_paths(vtx):
-    """One batch holding a tissue whose Hessian-product arrays fit in the
-    workgroup's LDS and one that does not (2600 cells in FP64: positions,
-    vector and two cell-coefficient pairs take ~250 KB): both equal the
-    single-tissue solve."""
+@pytest.mark.parametrize("block_threads", [1024, 512, 256])
+def test_batch_adjoint_lds_and_global_paths(vtx, block_threads):
+    """One batch holding tissues whose Hessian-product arrays fit in the
+    workgroup's LDS (120 and 1088 cells) and one that does not (2600 cells in
+    FP64: positions, vector and two cell-coefficient pairs take ~250 KB): all
+    equal the single-tissue solve.  With 512 or 256 threads the 120-cell
+    tissue takes the register-resident CG and the 1088-cell one (more cells
+    than two per thread) the general loop in LDS."""
     rng = np.random.default_rng(61)
     s = np.sqrt(2.0 / (3.0 * np.sqrt(3.0)))  # unit-area hexagons
     Ts, Xs, Ps, bs, singles = [], [], [], [], []
-    for nx, ny in [(12, 10), (52, 50)]:
+    for nx, ny in [(12, 10), (34, 32), (52, 50)]:
         t = g.hex_lattice(nx, ny, s)
         need = 32 * t.n_vert + 32 * t.n_cell  # FP64 bytes of the four arrays
-        assert need < 64 * 1024 if nx == 12 else need > 160 * 1024
+        assert need < 150 * 1024 if nx < 52 else need > 160 * 1024
         # the regular tiling with uniform tension is an equilibrium by
         # symmetry, and a stable one below the hexagon's shape index 3.72
         p = g.uniform_params(t, P0=3.7)
@@ -713,7 +721,8 @@ def test_batch_adjoint_lds_and_global_paths(vtx):
         gs, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-10)
         assert info["status"] == 0, info
         Ts.append(T); Xs.append(X); Ps.append(P); bs.append(b); singles.append(gs.cpu().numpy())
-    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10)
+    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10,
+                                           block_threads=block_threads)
     for gsingle, gb, inf in zip(singles, outs, infos):
         assert inf["status"] == 0, inf
         assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-7 * np.abs(gsingle).max()
