@@ -726,6 +726,15 @@ def test_batch_adjoint_lds_and_global_paths(vtx, block_threads):
     for gsingle, gb, inf in zip(singles, outs, infos):
         assert inf["status"] == 0, inf
         assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-7 * np.abs(gsingle).max()
+    if block_threads == 1024:
+        # the library's own choice (1024 here: one tissue has too many cells
+        # for the register-resident form) gives the same gradients
+        outs0, _ = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=0)
+        for a, b_ in zip(outs0, outs):
+            assert torch.equal(a, b_)
+        with pytest.raises(vtx.VtxError) as err:
+            vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=128)
+        assert err.value.code == -1
 
 
 @pytest.mark.parametrize("method", ["ep", "ep_forward"])
