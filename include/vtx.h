@@ -295,7 +295,12 @@ int vtx_batch_destroy(vtx_batch b);
  *                         workgroup of `block_threads` (256, 512 or 1024)
  *                         threads per tissue looping the whole relaxation,
  *                         tissues taken from a device work queue in
- *                         descending size;
+ *                         descending size; with T1 off and 512 threads, a
+ *                         batch whose tissues all have at most 1024 cells
+ *                         and fit the per-workgroup LDS (both position
+ *                         buffers, cell coefficients, corner rows) runs a
+ *                         kernel that keeps them there and the vertex stars
+ *                         in registers;
  *   VTX_SCHED_GRID        each tissue in turn through vtx_relax (all
  *                         workgroups of the GPU on one tissue; suits a few
  *                         large tissues); block_threads is ignored;
@@ -330,7 +335,8 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
  * (same arithmetic in every form).  0 takes 512 threads when every tissue
  * has that form, else 1024.  EP_CENTRED / EP_FORWARD: batched nudged
  * relaxations (vtx_batch_relax with a per-tissue nudge, workgroups of
- * `block_threads`, 0 meaning 1024) and one estimate launch.  X_star, p, dC_dX, X_target
+ * `block_threads`; 0 takes the LDS-resident relaxation of vtx_batch_relax
+ * when every tissue fits it, else 1024 threads) and one estimate launch.  X_star, p, dC_dX, X_target
  * and dC_dtheta are host arrays of n entries (device pointers inside; dC_dX
  * or X_target may be NULL as for vtx_param_grad).  Results go to the host
  * array res[n]; synchronises.  Errors: VTX_E_ARG (null arrays, bad mode,

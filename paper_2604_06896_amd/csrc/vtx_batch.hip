@@ -648,6 +648,285 @@ __device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int nc
     __syncthreads();
 }
 
+// Energy (+ beta C) at the positions returned in B.X and the tissue's result
+// record: the end of a batched relaxation.
+template <typename PosT>
+__device__ __forceinline__ void batch_relax_result(const BatchItem &B, const DevTissue &t,
+                                                   const DevParams<PosT> &p,
+                                                   const RelaxState &st, double *sh,
+                                                   vtx_relax_result *res, int idx) {
+    // energy at the returned positions
+    double e = 0.0;
+    const PosT *Xr = (const PosT *)B.X;
+    for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
+        const int rb = t.row_ptr[c], nn = t.nsides[c];
+        PosT A, P;
+        cell_geom<PosT, PosT>(
+            t, Xr, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
+            nullptr, nullptr);
+        const double da = (double)A - (double)p.a0(c), dp = (double)P - (double)p.p0(c);
+        e += (double)p.ka(c) * da * da + (double)p.kp(c) * dp * dp;
+    }
+    for (int k = threadIdx.x; k < t.n_edge; k += blockDim.x) {
+        const int32_t *r = t.he + 8 * (int64_t)t.edge_he[k];
+        const double dx = pdiff<double>((double)Xr[2 * (int64_t)r[HG]], (double)Xr[2 * (int64_t)r[HS]], r[HOX], t.Lx);
+        const double dy = pdiff<double>((double)Xr[2 * (int64_t)r[HG] + 1], (double)Xr[2 * (int64_t)r[HS] + 1], r[HOY], t.Ly);
+        e += (double)p.lm(k) * sqrt(dx * dx + dy * dy);
+    }
+    if (B.beta != 0.0)
+        for (int v = threadIdx.x; v < t.n_vert; v += blockDim.x) {
+            if (B.Xt) {
+                const PosT *Xt = (const PosT *)B.Xt;
+                const double dx = min_image((double)Xr[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
+                const double dy = min_image((double)Xr[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
+                e += B.beta * (dx * dx + dy * dy) * 0.5 / (double)t.n_vert;
+            } else {
+                e += B.beta * (B.g_lin[2 * (int64_t)v] * (double)Xr[2 * (int64_t)v] +
+                               B.g_lin[2 * (int64_t)v + 1] * (double)Xr[2 * (int64_t)v + 1]);
+            }
+        }
+    const double E = block_sum(e, sh);
+    if (threadIdx.x == 0) {
+        vtx_relax_result r;
+        r.iters = st.iter;
+        r.n_t1 = st.n_t1;
+        r.n_stretch = st.n_st;
+        r.max_f = st.last_mf;
+        r.energy = E;
+        r.status = st.status;
+        res[idx] = r;
+    }
+}
+
+// LDS bytes of a batched relaxation without T1 held in LDS: both position
+// buffers, the cell coefficients and the corner rows.
+template <typename PosT, typename M>
+__host__ __device__ inline int64_t relax_lds_bytes(int64_t n_vert, int64_t n_cell,
+                                                   int64_t n_he) {
+    auto a16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    return 2 * a16(2 * n_vert * (int64_t)sizeof(PosT)) + a16(2 * n_cell * (int64_t)sizeof(M)) +
+           a16(4 * n_he);
+}
+
+// Cells (and twice as many vertices) per thread of k_batch_relax_lds.
+constexpr int kRelaxLdsK = 2;
+constexpr int kRelaxLdsThreads = 512;
+
+// Batched relaxation without T1 (the nudged relaxations of EP, or any batch
+// relaxed with T1 off) for tissues of at most two cells and four vertices per
+// thread of a 512-thread workgroup whose two position buffers, cell
+// coefficients and corner rows fit in LDS.  Thread i owns cells i + 512 k
+// and vertices i + 512 j; their corner rows go to LDS and their star
+// entries, tensions, cell parameters and nudge targets to registers once, so
+// an iteration reads only LDS.  The cell pass, the nudge mean, the vertex
+// pass with the step and the convergence control are those of k_batch_relax
+// (same arithmetic; the nudge mean is summed per thread in the same vertex
+// order), and the state returned is copied back into the caller's buffer.
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
+    const BatchItem *__restrict__ items, const int32_t *__restrict__ order, int n,
+    unsigned int *queue, BatchOpts o, vtx_relax_result *res) {
+    constexpr int K = kRelaxLdsK, KV = 2 * kRelaxLdsK;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    __shared__ double sh[16];
+    __shared__ int s_item;
+    __shared__ int s_scan[16];
+    __shared__ RelaxState st;
+    __shared__ double s_mean[2];
+    auto a16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int slot = s_item;
+        __syncthreads();
+        if (slot >= n) return;
+        const int idx = order[slot];
+        const BatchItem &B = items[idx];
+        const DevTissue &t = B.t;
+        const DevParams<PosT> p = to_dev<PosT>(B.p);
+        const int tid = threadIdx.x, bd = blockDim.x, nv = t.n_vert, nc = t.n_cell;
+        const int64_t xb = a16(2 * (int64_t)nv * (int64_t)sizeof(PosT));
+        PosT *X0 = (PosT *)lds_dyn;
+        PosT *X1 = (PosT *)(lds_dyn + xb);
+        M *capl = (M *)(lds_dyn + 2 * xb);
+        int32_t *rowl = (int32_t *)(lds_dyn + 2 * xb + a16(2 * (int64_t)nc * (int64_t)sizeof(M)));
+        for (int k = tid; k < 2 * nv; k += bd) X0[k] = ((const PosT *)B.X)[k];
+        int cn[K], lrb[K];
+        PosT ka[K], a0[K], kp[K], p0[K];
+        int rows_base = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int c = tid + i * bd;
+            int rb = 0;
+            cn[i] = 0;
+            ka[i] = a0[i] = kp[i] = p0[i] = 0;
+            if (c < nc) {
+                rb = t.row_ptr[c];
+                cn[i] = t.nsides[c];
+                ka[i] = p.ka(c);
+                a0[i] = p.a0(c);
+                kp[i] = p.kp(c);
+                p0[i] = p.p0(c);
+            }
+            int tot;
+            lrb[i] = rows_base + block_exclusive_scan(cn[i], s_scan, tot);
+            rows_base += tot;
+            const int nk = min(cn[i], t.n_he - lrb[i]);  // the rows hold n_he corners in all
+            for (int k = 0; k < nk; ++k) rowl[lrb[i] + k] = t.corner[rb + k];
+        }
+        int32_t sw[KV][3], sc[KV][3];
+        PosT sl[KV][3];
+        double nt[KV][2];  // nudge target (v2v) or linear cost gradient
+#pragma unroll
+        for (int j = 0; j < KV; ++j) {
+            const int v = tid + j * bd;
+            nt[j][0] = nt[j][1] = 0.0;
+            if (v < nv) {
+                const int4 a = reinterpret_cast<const int4 *>(t.star)[v];
+                const int4 b = reinterpret_cast<const int4 *>(t.star + 4 * (int64_t)nv)[v];
+                const int32_t e[3] = {b.z, b.w, t.star[8 * (int64_t)nv + v]};
+                sw[j][0] = a.x;
+                sw[j][1] = a.y;
+                sw[j][2] = a.z;
+                sc[j][0] = a.w;
+                sc[j][1] = b.x;
+                sc[j][2] = b.y;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sl[j][k] = p.lam ? p.lam[e[k]] : p.lam_s;
+                if (B.beta != 0.0) {
+                    if (B.Xt) {
+                        const PosT *Xt = (const PosT *)B.Xt;
+                        nt[j][0] = (double)Xt[2 * (int64_t)v];
+                        nt[j][1] = (double)Xt[2 * (int64_t)v + 1];
+                    } else {
+                        nt[j][0] = B.g_lin[2 * (int64_t)v];
+                        nt[j][1] = B.g_lin[2 * (int64_t)v + 1];
+                    }
+                }
+            }
+        }
+        if (tid == 0) st = RelaxState{0, 0, 0, 0, 0.0, VTX_NOT_CONVERGED, 0, 0, 0, 0};
+        __syncthreads();
+        const double inv_n = 1.0 / (double)nv;
+        // gradient of the nudge cost at own vertex j (as nudge_grad)
+        auto nudge = [&](int j, const PosT *Xc, int v, double &cx, double &cy) {
+            if (B.Xt) {
+                cx = min_image((double)Xc[2 * v] - nt[j][0], t.Lx) * inv_n;
+                cy = min_image((double)Xc[2 * v + 1] - nt[j][1], t.Ly) * inv_n;
+            } else {
+                cx = nt[j][0];
+                cy = nt[j][1];
+            }
+        };
+        int cur = 0;
+        for (;;) {
+            const PosT *Xc = cur ? X1 : X0;
+            PosT *Xn = cur ? X0 : X1;
+            // cell pass
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int c = tid + i * bd;
+                const int base = lrb[i];
+                if (c < nc) {
+                    PosT A, P;
+                    cell_geom<PosT, PosT>(
+                        t, Xc, cn[i], [&](int k) { return rowl[base + k]; }, 0, A, P, false,
+                        (PosT)0, nullptr, nullptr);
+                    st2(capl, c, (M)((PosT)2 * ka[i] * (A - a0[i])),
+                        (M)((PosT)2 * kp[i] * (P - p0[i])));
+                }
+            }
+            __syncthreads();
+            // mean of the nudge gradient over the vertices
+            double mx = 0.0, my = 0.0;
+            if (B.beta != 0.0) {
+                double sx = 0.0, sy = 0.0;
+#pragma unroll
+                for (int j = 0; j < KV; ++j) {
+                    const int v = tid + j * bd;
+                    if (v < nv) {
+                        double cx, cy;
+                        nudge(j, Xc, v, cx, cy);
+                        sx += cx;
+                        sy += cy;
+                    }
+                }
+                const double bx = block_sum(sx, sh);
+                const double by = block_sum(sy, sh);
+                if (tid == 0) {
+                    s_mean[0] = bx * inv_n;
+                    s_mean[1] = by * inv_n;
+                }
+                __syncthreads();
+                mx = s_mean[0];
+                my = s_mean[1];
+            }
+            // vertex pass with the step
+            double mf = 0.0;
+#pragma unroll
+            for (int j = 0; j < KV; ++j) {
+                const int v = tid + j * bd;
+                if (v < nv) {
+                    StarLoad<PosT, M> L;
+                    L.pi = ld2(Xc, v);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        L.w[k] = sw[j][k];
+                        L.c[k] = sc[j][k];
+                        L.lam[k] = sl[j][k];
+                        L.q[k] = ld2(Xc, id_of(L.w[k]));
+                        L.cc[k] = ld2(capl, L.c[k]);
+                    }
+                    Star<PosT, M> s;
+                    PosT xi, yi;
+                    star_math<PosT, M>(t, L, s, xi, yi);
+                    M fx, fy;
+                    star_force<PosT, M>(s, fx, fy);
+                    double gx = fx, gy = fy;
+                    if (B.beta != 0.0) {
+                        double cx, cy;
+                        nudge(j, Xc, v, cx, cy);
+                        gx -= B.beta * (cx - mx);
+                        gy -= B.beta * (cy - my);
+                    }
+                    mf = fmax(mf, fmax(fabs(gx), fabs(gy)));
+                    if (!(gx == gx) || !(gy == gy)) mf = INFINITY;
+                    st2(Xn, v, (PosT)((double)xi + o.eta * gx), (PosT)((double)yi + o.eta * gy));
+                }
+            }
+            const double m = block_max(mf, sh);
+            if (tid == 0) {
+                st.iter += 1;
+                st.last_mf = m;
+                if (!(m <= 1.7976931348623157e308)) {
+                    st.done = 1;
+                    st.status = VTX_E_NONFINITE;
+                    st.result_buf = cur;
+                } else {
+                    st.count = m < o.tol ? st.count + 1 : 0;
+                    if (st.count >= o.patience) {
+                        st.done = 1;
+                        st.status = VTX_CONVERGED;
+                        st.result_buf = cur;
+                    } else if (st.iter >= o.max_iter) {
+                        st.done = 1;
+                        st.status = VTX_NOT_CONVERGED;
+                        st.result_buf = cur ^ 1;
+                    }
+                }
+            }
+            __syncthreads();
+            if (st.done) break;
+            cur ^= 1;
+        }
+        const PosT *Xr = st.result_buf ? X1 : X0;
+        for (int k = tid; k < 2 * nv; k += bd) ((PosT *)B.X)[k] = Xr[k];
+        __syncthreads();
+        batch_relax_result<PosT>(B, t, p, st, sh, res, idx);
+        __syncthreads();
+    }
+}
+
 // Persistent batched relaxation (Methods, "Simulation engine", per tissue):
 // each workgroup takes tissues from a device queue (largest first) and runs
 // the whole gradient-descent loop of one tissue with workgroup barriers
@@ -782,47 +1061,7 @@ __global__ __launch_bounds__(1024) void k_batch_relax(const BatchItem *__restric
             for (int k = threadIdx.x; k < 2 * t.n_vert; k += blockDim.x)
                 ((PosT *)B.X)[k] = ((PosT *)B.xbuf)[k];
         __syncthreads();
-        // energy at the returned positions
-        double e = 0.0;
-        const PosT *Xr = (const PosT *)B.X;
-        for (int c = threadIdx.x; c < t.n_cell; c += blockDim.x) {
-            const int rb = t.row_ptr[c], nn = t.nsides[c];
-            PosT A, P;
-            cell_geom<PosT, PosT>(
-                t, Xr, nn, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
-                nullptr, nullptr);
-            const double da = (double)A - (double)p.a0(c), dp = (double)P - (double)p.p0(c);
-            e += (double)p.ka(c) * da * da + (double)p.kp(c) * dp * dp;
-        }
-        for (int k = threadIdx.x; k < t.n_edge; k += blockDim.x) {
-            const int32_t *r = t.he + 8 * (int64_t)t.edge_he[k];
-            const double dx = pdiff<double>((double)Xr[2 * (int64_t)r[HG]], (double)Xr[2 * (int64_t)r[HS]], r[HOX], t.Lx);
-            const double dy = pdiff<double>((double)Xr[2 * (int64_t)r[HG] + 1], (double)Xr[2 * (int64_t)r[HS] + 1], r[HOY], t.Ly);
-            e += (double)p.lm(k) * sqrt(dx * dx + dy * dy);
-        }
-        if (B.beta != 0.0)
-            for (int v = threadIdx.x; v < t.n_vert; v += blockDim.x) {
-                if (B.Xt) {
-                    const PosT *Xt = (const PosT *)B.Xt;
-                    const double dx = min_image((double)Xr[2 * (int64_t)v] - (double)Xt[2 * (int64_t)v], t.Lx);
-                    const double dy = min_image((double)Xr[2 * (int64_t)v + 1] - (double)Xt[2 * (int64_t)v + 1], t.Ly);
-                    e += B.beta * (dx * dx + dy * dy) * 0.5 / (double)t.n_vert;
-                } else {
-                    e += B.beta * (B.g_lin[2 * (int64_t)v] * (double)Xr[2 * (int64_t)v] +
-                                   B.g_lin[2 * (int64_t)v + 1] * (double)Xr[2 * (int64_t)v + 1]);
-                }
-            }
-        const double E = block_sum(e, sh);
-        if (threadIdx.x == 0) {
-            vtx_relax_result r;
-            r.iters = st.iter;
-            r.n_t1 = st.n_t1;
-            r.n_stretch = st.n_st;
-            r.max_f = st.last_mf;
-            r.energy = E;
-            r.status = st.status;
-            res[idx] = r;
-        }
+        batch_relax_result<PosT>(B, t, p, st, sh, res, idx);
         __syncthreads();
     }
 }
@@ -925,6 +1164,36 @@ int launch_batch_cg(vtx_batch b, const GradItem *gi, int n, const GradOpts &go,
                : launch_batch_cg_t<PosT, M, 1024>(b, gi, n, go, block_threads, s);
 }
 
+// Dynamic LDS for k_batch_relax_lds if every tissue of the batch fits it
+// (*lds > 0), else *lds = 0.
+template <typename PosT, typename M>
+int relax_lds_plan(vtx_batch b, int *lds) {
+    *lds = 0;
+    int dev = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    hipFuncAttributes fa{};
+    if (e == hipSuccess)
+        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M>));
+    if (e != hipSuccess) return hip_fail(e);
+    const int64_t budget = (int64_t)lds_max - (int64_t)fa.sharedSizeBytes;
+    int64_t need = 0;
+    for (size_t i = 0; i < b->ts.size(); ++i) {
+        const DevTissue &d = tissue_dev(b->ts[i]);
+        const int64_t nb = relax_lds_bytes<PosT, M>(d.n_vert, d.n_cell, d.n_he);
+        if (d.n_cell > (int64_t)kRelaxLdsK * kRelaxLdsThreads ||
+            d.n_vert > 2 * (int64_t)kRelaxLdsK * kRelaxLdsThreads || nb > budget)
+            return VTX_OK;
+        need = nb > need ? nb : need;
+    }
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+    if (e != hipSuccess) return hip_fail(e);
+    *lds = (int)need;
+    return VTX_OK;
+}
+
 int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
                     const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
                     double beta, int block_threads, vtx_relax_result *res, hipStream_t s) {
@@ -950,9 +1219,30 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     if (e != hipSuccess) return hip_fail(e);
     BatchOpts bo{o->eta, o->tol, o->l_min, o->l_new, o->patience, o->max_iter, o->t1_enable};
     const BatchItem *it = (const BatchItem *)b->items;
+    // Without T1, a batch whose every tissue fits k_batch_relax_lds runs there
+    // when the caller asked for its workgroup size or left the choice open.
+    int lds = 0;
+    if (!o->t1_enable && (block_threads == 0 || block_threads == kRelaxLdsThreads)) {
+        const int rc = mode == VTX_F32   ? relax_lds_plan<float, float>(b, &lds)
+                       : mode == VTX_F64 ? relax_lds_plan<double, double>(b, &lds)
+                                         : relax_lds_plan<double, float>(b, &lds);
+        if (rc) return rc;
+    }
+    if (block_threads == 0) block_threads = 1024;
     int rc = run_graph(b, s, [&](hipStream_t cs) {
         const dim3 grid(n), block(block_threads);
-        if (mode == VTX_F32)
+        if (lds > 0) {
+            const dim3 bl(kRelaxLdsThreads);
+            if (mode == VTX_F32)
+                hipLaunchKernelGGL((k_batch_relax_lds<float, float>), grid, bl, (size_t)lds, cs, it,
+                                   b->order_d, n, b->queue, bo, b->res_d);
+            else if (mode == VTX_F64)
+                hipLaunchKernelGGL((k_batch_relax_lds<double, double>), grid, bl, (size_t)lds, cs,
+                                   it, b->order_d, n, b->queue, bo, b->res_d);
+            else
+                hipLaunchKernelGGL((k_batch_relax_lds<double, float>), grid, bl, (size_t)lds, cs,
+                                   it, b->order_d, n, b->queue, bo, b->res_d);
+        } else if (mode == VTX_F32)
             hipLaunchKernelGGL((k_batch_relax<float, float>), grid, block, 0, cs, it, b->order_d,
                                n, b->queue, bo, b->res_d);
         else if (mode == VTX_F64)
@@ -1195,7 +1485,6 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
     }
     if (o->method != VTX_GRAD_EP_CENTRED && o->method != VTX_GRAD_EP_FORWARD)
         return set_error(VTX_E_ARG, "unknown method");
-    if (block_threads == 0) block_threads = 1024;
     const bool centred = o->method == VTX_GRAD_EP_CENTRED;
     if (!(o->beta != 0.0)) return set_error(VTX_E_ARG, "EP needs beta != 0");
     if (o->ep_relax.t1_enable) return set_error(VTX_E_ARG, "EP relaxations cannot use T1");

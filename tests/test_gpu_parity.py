@@ -590,6 +590,39 @@ def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
         assert st[0] == 0 and st[2] == 0 and st[4] == 1
 
 
+@pytest.mark.parametrize("mode", ["f64", "mixed", "f32"])
+def test_batch_relax_without_t1_in_lds(vtx, errlog, mode):
+    """Without T1 and with 512 threads, a batch of tissues of 64-1000 cells
+    runs in the LDS-resident relaxation kernel and a batch that also holds a
+    1100-cell tissue (more than two cells per thread) in the general one:
+    both reproduce the single-tissue path."""
+    rng = np.random.default_rng(43)
+    cases = [_batch_case(rng, n, P0) for n, P0 in ((64, 3.65), (300, 3.70), (1000, 3.72))]
+    big = _batch_case(rng, 1100, 3.70)
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=20000, t1_enable=False)
+    dt = vtx.pos_dtype(mode)
+    refs = {}
+    for k, (t, p) in enumerate(cases + [big]):
+        T = vtx.Tissue.from_tissue(t)
+        Xd = _dev(t.X, dt)
+        r = T.relax(Xd, vtx.Params.from_numpy(p, dtype=dt), mode=mode, **opts)
+        refs[k] = (r, Xd.cpu().numpy())
+    for batch in (cases, cases + [big]):
+        Ts = [vtx.Tissue.from_tissue(t) for t, _ in batch]
+        Xs = [_dev(t.X, dt) for t, _ in batch]
+        res = vtx.Batch(Ts).relax(Xs, [vtx.Params.from_numpy(p, dtype=dt) for _, p in batch],
+                                  mode=mode, block_threads=512, **opts)
+        for k, (r, X) in enumerate(zip(res, Xs)):
+            rs, Xref = refs[k]
+            assert (r["status"], r["iters"]) == (rs["status"], rs["iters"])
+            d = np.abs(X.cpu().numpy() - Xref).max()
+            errlog(f"batched (LDS-resident when it fits) vs single relaxation without T1, {mode}, "
+                   f"{Ts[k].n_cell} cells: positions (max abs)", d)
+            assert d < 1e-9
+            assert r["energy"] == pytest.approx(
+                rs["energy"], rel={"f64": 1e-9, "mixed": 1e-7, "f32": 1e-6}[mode])
+
+
 def test_split_passes_equal_full_evaluation(vtx, oracle):
     t, p = g.workload_single_10k(n_cell=3000, seed=5)
     T = vtx.Tissue.from_tissue(t)
