@@ -187,6 +187,44 @@ def test_cells_with_many_sides(vtx, oracle):
     assert np.abs(Xd.cpu().numpy() - X).max() < 1e-12
 
 
+def test_batched_lds_paths_with_many_sided_cells(vtx, small_equilibria):
+    """The LDS-resident relaxation (no T1) and the register-resident batched
+    CG walk corner rows past their prefetched slots too: a batch of the
+    16-sided-cell tissue and a random one, run for a fixed number of
+    relaxation steps and then differentiated with 512 threads, equals the
+    single-tissue calls (the many-sided tissue is not at equilibrium, so its
+    CG may stop at negative curvature: the same step either way)."""
+    t0, p0 = _many_sided_tissue()
+    t1, m1, X1, p1, _ = small_equilibria[0]  # an equilibrium (with T1) of the oracle
+    t1 = g.Tissue(m1.he.copy(), X1.copy(), t1.Lx, t1.Ly)
+    cases = [(t0, p0, 4000), (t1, p1, 1000)]
+    singles = []
+    for t, p, iters in cases:
+        T = vtx.Tissue.from_tissue(t)
+        X = _dev(t.X)
+        P = vtx.Params.from_numpy(p)
+        r = T.relax(X, P, mode="f64", eta=3e-3, tol=1e-9, max_iter=iters, t1_enable=False)
+        b = _dev(np.random.default_rng(9).normal(size=t.X.shape))
+        gs, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-10)
+        singles.append((r, X.cpu().numpy(), b, gs.cpu().numpy(), info))
+    assert singles[1][0]["status"] == 0 and singles[1][4]["status"] == 0
+    Ts = [vtx.Tissue.from_tissue(t) for t, _, _ in cases]
+    Ps = [vtx.Params.from_numpy(p) for _, p, _ in cases]
+    Xs = []
+    for (t, p, iters), T, P, (rs, Xref, _, _, _) in zip(cases, Ts, Ps, singles):
+        X = _dev(t.X)
+        r = vtx.Batch([T]).relax([X], [P], mode="f64", block_threads=512, eta=3e-3, tol=1e-9,
+                                 max_iter=iters, t1_enable=False)[0]
+        assert (r["status"], r["iters"]) == (rs["status"], rs["iters"])
+        assert np.abs(X.cpu().numpy() - Xref).max() < 1e-9
+        Xs.append(X)
+    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=[s[2] for s in singles],
+                                           cg_tol=1e-10, block_threads=512)
+    for (_, _, _, gref, iref), gb, inf in zip(singles, outs, infos):
+        assert (inf["status"], inf["cg_iters"]) == (iref["status"], iref["cg_iters"])
+        assert np.abs(gb.cpu().numpy() - gref).max() < 1e-8 * np.abs(gref).max()
+
+
 # ----------------------------------------------------------------------- T1
 
 @pytest.mark.parametrize("mode", ["f64", "mixed"])
