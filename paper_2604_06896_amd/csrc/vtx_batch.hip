@@ -612,14 +612,14 @@ struct RelaxState {
 
 // One T1 pass of a batched tissue (block-wide): sort the candidate edges,
 // run the sequential pass in one wave, compact the rows if one moved to the
-// pool.  Not inlined, and it receives the tissue only by address: the pass
-// needs many registers, and a caller that kept its own copies of the tissue
-// and parameters live across the call would spill them inside the cell and
-// vertex loops.
+// pool.  Called through the non-inlined wrappers below, which receive the
+// tissue only by address: the pass needs many registers, and a caller that
+// kept its own copies of the tissue and parameters live across the call
+// would spill them inside the cell and vertex loops.
 template <typename PosT, typename M>
-__device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int ncand,
-                                           double l_min, double l_new, int32_t *sort_buf,
-                                           int32_t *extra, int32_t *scan, RelaxState *st) {
+__device__ __forceinline__ void t1_pass_body(const BatchItem *Bp, PosT *Xc, M *cap, int ncand,
+                                             double l_min, double l_new, int32_t *sort_buf,
+                                             int32_t *extra, int32_t *scan, RelaxState *st) {
     const BatchItem &B = *Bp;
     const DevTissue &t = B.t;
     const DevParams<PosT> p = to_dev<PosT>(B.p);
@@ -631,8 +631,7 @@ __device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int nc
     __syncthreads();
     block_bitonic(arr, np2);
     if (threadIdx.x < 64) {  // one wave runs the pass
-        T1Counts r = t1_sequential<PosT, M>(t, Xc, p, (M *)B.cap, arr, ncand, extra, l_min,
-                                            l_new);
+        T1Counts r = t1_sequential<PosT, M>(t, Xc, p, cap, arr, ncand, extra, l_min, l_new);
         if (threadIdx.x == 0) {
             st->n_t1 += r.swaps;
             st->n_st += r.stretches;
@@ -646,6 +645,21 @@ __device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int nc
         if (threadIdx.x == 0 && bad) st->bad_t1 = 2;
     }
     __syncthreads();
+}
+
+template <typename PosT, typename M>
+__device__ __noinline__ void batch_t1_pass(const BatchItem *Bp, PosT *Xc, int ncand,
+                                           double l_min, double l_new, int32_t *sort_buf,
+                                           int32_t *extra, int32_t *scan, RelaxState *st) {
+    t1_pass_body<PosT, M>(Bp, Xc, (M *)Bp->cap, ncand, l_min, l_new, sort_buf, extra, scan, st);
+}
+
+// The same pass for a tissue whose positions and coefficients are in LDS.
+template <typename PosT, typename M>
+__device__ __noinline__ void batch_t1_pass_lds(const BatchItem *Bp, PosT *Xc, M *cap, int ncand,
+                                               double l_min, double l_new, int32_t *sort_buf,
+                                               int32_t *extra, int32_t *scan, RelaxState *st) {
+    t1_pass_body<PosT, M>(Bp, Xc, cap, ncand, l_min, l_new, sort_buf, extra, scan, st);
 }
 
 // Energy (+ beta C) at the positions returned in B.X and the tissue's result
@@ -712,28 +726,35 @@ __host__ __device__ inline int64_t relax_lds_bytes(int64_t n_vert, int64_t n_cel
 constexpr int kRelaxLdsK = 2;
 constexpr int kRelaxLdsThreads = 512;
 
-// Batched relaxation without T1 (the nudged relaxations of EP, or any batch
-// relaxed with T1 off) for tissues of at most two cells and four vertices per
+// Batched relaxation of tissues of at most two cells and four vertices per
 // thread of a 512-thread workgroup whose two position buffers, cell
 // coefficients and corner rows fit in LDS.  Thread i owns cells i + 512 k
 // and vertices i + 512 j; their corner rows go to LDS and their star
-// entries, tensions, cell parameters and nudge targets to registers once, so
-// an iteration reads only LDS.  The cell pass, the nudge mean, the vertex
+// entries, tensions, cell parameters and nudge targets to registers, so an
+// iteration reads only LDS.  With T1 (the T1 template flag) the cell pass
+// also flags short edges, the pass runs on the LDS positions and
+// coefficients, and the rows and stars are loaded again after it (a pass
+// edits them in global memory).  The cell pass, the nudge mean, the vertex
 // pass with the step and the convergence control are those of k_batch_relax
 // (same arithmetic; the nudge mean is summed per thread in the same vertex
 // order), and the state returned is copied back into the caller's buffer.
-template <typename PosT, typename M>
+template <typename PosT, typename M, bool T1>
 __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
     const BatchItem *__restrict__ items, const int32_t *__restrict__ order, int n,
     unsigned int *queue, BatchOpts o, vtx_relax_result *res) {
     constexpr int K = kRelaxLdsK, KV = 2 * kRelaxLdsK;
     extern __shared__ __align__(16) unsigned char lds_dyn[];
+    __shared__ int32_t sort_buf[T1 ? kT1SortCap : 1];
+    __shared__ int32_t extra[T1 ? kT1Extra : 1];
+    __shared__ int32_t scan[T1 ? kRelaxLdsThreads : 1];
+    __shared__ unsigned int s_cnt;
     __shared__ double sh[16];
     __shared__ int s_item;
     __shared__ int s_scan[16];
     __shared__ RelaxState st;
     __shared__ double s_mean[2];
     auto a16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
+    const M lmin2 = (M)(o.l_min * o.l_min * (1.0 + 1e-4));
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -751,57 +772,72 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
         M *capl = (M *)(lds_dyn + 2 * xb);
         int32_t *rowl = (int32_t *)(lds_dyn + 2 * xb + a16(2 * (int64_t)nc * (int64_t)sizeof(M)));
         for (int k = tid; k < 2 * nv; k += bd) X0[k] = ((const PosT *)B.X)[k];
-        int cn[K], lrb[K];
+        int cn[K], lrb[K], grb[K];
         PosT ka[K], a0[K], kp[K], p0[K];
-        int rows_base = 0;
+        int32_t sw[KV][3], sc[KV][3];
+        PosT sl[KV][3];
+        // the topology a step reads: rows into LDS, stars and tensions into
+        // registers (again after every T1 pass)
+        auto load_topology = [&]() {
+            int rows_base = 0;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int c = tid + i * bd;
+                grb[i] = 0;
+                cn[i] = 0;
+                if (c < nc) {
+                    grb[i] = t.row_ptr[c];
+                    cn[i] = t.nsides[c];
+                }
+                int tot;
+                lrb[i] = rows_base + block_exclusive_scan(cn[i], s_scan, tot);
+                rows_base += tot;
+                const int nk = min(cn[i], t.n_he - lrb[i]);  // the rows hold n_he corners
+                for (int k = 0; k < nk; ++k) rowl[lrb[i] + k] = t.corner[grb[i] + k];
+            }
+#pragma unroll
+            for (int j = 0; j < KV; ++j) {
+                const int v = tid + j * bd;
+                if (v < nv) {
+                    const int4 a = reinterpret_cast<const int4 *>(t.star)[v];
+                    const int4 b = reinterpret_cast<const int4 *>(t.star + 4 * (int64_t)nv)[v];
+                    const int32_t e[3] = {b.z, b.w, t.star[8 * (int64_t)nv + v]};
+                    sw[j][0] = a.x;
+                    sw[j][1] = a.y;
+                    sw[j][2] = a.z;
+                    sc[j][0] = a.w;
+                    sc[j][1] = b.x;
+                    sc[j][2] = b.y;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) sl[j][k] = p.lam ? p.lam[e[k]] : p.lam_s;
+                }
+            }
+        };
+        load_topology();
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int c = tid + i * bd;
-            int rb = 0;
-            cn[i] = 0;
             ka[i] = a0[i] = kp[i] = p0[i] = 0;
             if (c < nc) {
-                rb = t.row_ptr[c];
-                cn[i] = t.nsides[c];
                 ka[i] = p.ka(c);
                 a0[i] = p.a0(c);
                 kp[i] = p.kp(c);
                 p0[i] = p.p0(c);
             }
-            int tot;
-            lrb[i] = rows_base + block_exclusive_scan(cn[i], s_scan, tot);
-            rows_base += tot;
-            const int nk = min(cn[i], t.n_he - lrb[i]);  // the rows hold n_he corners in all
-            for (int k = 0; k < nk; ++k) rowl[lrb[i] + k] = t.corner[rb + k];
         }
-        int32_t sw[KV][3], sc[KV][3];
-        PosT sl[KV][3];
         double nt[KV][2];  // nudge target (v2v) or linear cost gradient
 #pragma unroll
         for (int j = 0; j < KV; ++j) {
             const int v = tid + j * bd;
             nt[j][0] = nt[j][1] = 0.0;
-            if (v < nv) {
-                const int4 a = reinterpret_cast<const int4 *>(t.star)[v];
-                const int4 b = reinterpret_cast<const int4 *>(t.star + 4 * (int64_t)nv)[v];
-                const int32_t e[3] = {b.z, b.w, t.star[8 * (int64_t)nv + v]};
-                sw[j][0] = a.x;
-                sw[j][1] = a.y;
-                sw[j][2] = a.z;
-                sc[j][0] = a.w;
-                sc[j][1] = b.x;
-                sc[j][2] = b.y;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) sl[j][k] = p.lam ? p.lam[e[k]] : p.lam_s;
-                if (B.beta != 0.0) {
-                    if (B.Xt) {
-                        const PosT *Xt = (const PosT *)B.Xt;
-                        nt[j][0] = (double)Xt[2 * (int64_t)v];
-                        nt[j][1] = (double)Xt[2 * (int64_t)v + 1];
-                    } else {
-                        nt[j][0] = B.g_lin[2 * (int64_t)v];
-                        nt[j][1] = B.g_lin[2 * (int64_t)v + 1];
-                    }
+            if (v < nv && B.beta != 0.0) {
+                if (B.Xt) {
+                    const PosT *Xt = (const PosT *)B.Xt;
+                    nt[j][0] = (double)Xt[2 * (int64_t)v];
+                    nt[j][1] = (double)Xt[2 * (int64_t)v + 1];
+                } else {
+                    nt[j][0] = B.g_lin[2 * (int64_t)v];
+                    nt[j][1] = B.g_lin[2 * (int64_t)v + 1];
                 }
             }
         }
@@ -818,10 +854,15 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                 cy = nt[j][1];
             }
         };
+        const PosT lmin2p = (PosT)lmin2;
         int cur = 0;
         for (;;) {
-            const PosT *Xc = cur ? X1 : X0;
+            PosT *Xc = cur ? X1 : X0;
             PosT *Xn = cur ? X0 : X1;
+            if (T1) {
+                if (tid == 0) s_cnt = 0u;
+                __syncthreads();
+            }
             // cell pass
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -830,13 +871,22 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                 if (c < nc) {
                     PosT A, P;
                     cell_geom<PosT, PosT>(
-                        t, Xc, cn[i], [&](int k) { return rowl[base + k]; }, 0, A, P, false,
-                        (PosT)0, nullptr, nullptr);
+                        t, Xc, cn[i], [&](int k) { return rowl[base + k]; }, grb[i], A, P,
+                        T1 && o.t1_enable != 0, lmin2p, B.t1_list, &s_cnt);
                     st2(capl, c, (M)((PosT)2 * ka[i] * (A - a0[i])),
                         (M)((PosT)2 * kp[i] * (P - p0[i])));
                 }
             }
             __syncthreads();
+            if (T1) {
+                const int ncand = (int)s_cnt;
+                if (ncand > 0) {
+                    batch_t1_pass_lds<PosT, M>(&B, Xc, capl, ncand, o.l_min, o.l_new, sort_buf,
+                                               extra, scan, &st);
+                    load_topology();
+                    __syncthreads();
+                }
+            }
             // mean of the nudge gradient over the vertices
             double mx = 0.0, my = 0.0;
             if (B.beta != 0.0) {
@@ -898,7 +948,11 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
             if (tid == 0) {
                 st.iter += 1;
                 st.last_mf = m;
-                if (!(m <= 1.7976931348623157e308)) {
+                if (st.bad_t1) {
+                    st.done = 1;
+                    st.status = VTX_E_CAPACITY;
+                    st.result_buf = cur;
+                } else if (!(m <= 1.7976931348623157e308)) {
                     st.done = 1;
                     st.status = VTX_E_NONFINITE;
                     st.result_buf = cur;
@@ -1166,7 +1220,7 @@ int launch_batch_cg(vtx_batch b, const GradItem *gi, int n, const GradOpts &go,
 
 // Dynamic LDS for k_batch_relax_lds if every tissue of the batch fits it
 // (*lds > 0), else *lds = 0.
-template <typename PosT, typename M>
+template <typename PosT, typename M, bool T1>
 int relax_lds_plan(vtx_batch b, int *lds) {
     *lds = 0;
     int dev = 0, lds_max = 0;
@@ -1175,7 +1229,8 @@ int relax_lds_plan(vtx_batch b, int *lds) {
         e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     hipFuncAttributes fa{};
     if (e == hipSuccess)
-        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M>));
+        e = hipFuncGetAttributes(&fa,
+                                 reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M, T1>));
     if (e != hipSuccess) return hip_fail(e);
     const int64_t budget = (int64_t)lds_max - (int64_t)fa.sharedSizeBytes;
     int64_t need = 0;
@@ -1187,7 +1242,7 @@ int relax_lds_plan(vtx_batch b, int *lds) {
             return VTX_OK;
         need = nb > need ? nb : need;
     }
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_relax_lds<PosT, M, T1>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
     if (e != hipSuccess) return hip_fail(e);
     *lds = (int)need;
@@ -1219,29 +1274,40 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     if (e != hipSuccess) return hip_fail(e);
     BatchOpts bo{o->eta, o->tol, o->l_min, o->l_new, o->patience, o->max_iter, o->t1_enable};
     const BatchItem *it = (const BatchItem *)b->items;
-    // Without T1, a batch whose every tissue fits k_batch_relax_lds runs there
-    // when the caller asked for its workgroup size or left the choice open.
+    // A batch whose every tissue fits k_batch_relax_lds runs there when the
+    // caller asked for its workgroup size or left the choice open.
     int lds = 0;
-    if (!o->t1_enable && (block_threads == 0 || block_threads == kRelaxLdsThreads)) {
-        const int rc = mode == VTX_F32   ? relax_lds_plan<float, float>(b, &lds)
-                       : mode == VTX_F64 ? relax_lds_plan<double, double>(b, &lds)
-                                         : relax_lds_plan<double, float>(b, &lds);
+    const bool t1 = o->t1_enable != 0;
+    if (block_threads == 0 || block_threads == kRelaxLdsThreads) {
+        int rc;
+        if (mode == VTX_F32)
+            rc = t1 ? relax_lds_plan<float, float, true>(b, &lds)
+                    : relax_lds_plan<float, float, false>(b, &lds);
+        else if (mode == VTX_F64)
+            rc = t1 ? relax_lds_plan<double, double, true>(b, &lds)
+                    : relax_lds_plan<double, double, false>(b, &lds);
+        else
+            rc = t1 ? relax_lds_plan<double, float, true>(b, &lds)
+                    : relax_lds_plan<double, float, false>(b, &lds);
         if (rc) return rc;
     }
     if (block_threads == 0) block_threads = 1024;
+    auto launch_lds = [&](auto kern, hipStream_t cs) {
+        hipLaunchKernelGGL(kern, dim3(n), dim3(kRelaxLdsThreads), (size_t)lds, cs, it, b->order_d,
+                           n, b->queue, bo, b->res_d);
+    };
     int rc = run_graph(b, s, [&](hipStream_t cs) {
         const dim3 grid(n), block(block_threads);
         if (lds > 0) {
-            const dim3 bl(kRelaxLdsThreads);
             if (mode == VTX_F32)
-                hipLaunchKernelGGL((k_batch_relax_lds<float, float>), grid, bl, (size_t)lds, cs, it,
-                                   b->order_d, n, b->queue, bo, b->res_d);
+                t1 ? launch_lds(k_batch_relax_lds<float, float, true>, cs)
+                   : launch_lds(k_batch_relax_lds<float, float, false>, cs);
             else if (mode == VTX_F64)
-                hipLaunchKernelGGL((k_batch_relax_lds<double, double>), grid, bl, (size_t)lds, cs,
-                                   it, b->order_d, n, b->queue, bo, b->res_d);
+                t1 ? launch_lds(k_batch_relax_lds<double, double, true>, cs)
+                   : launch_lds(k_batch_relax_lds<double, double, false>, cs);
             else
-                hipLaunchKernelGGL((k_batch_relax_lds<double, float>), grid, bl, (size_t)lds, cs,
-                                   it, b->order_d, n, b->queue, bo, b->res_d);
+                t1 ? launch_lds(k_batch_relax_lds<double, float, true>, cs)
+                   : launch_lds(k_batch_relax_lds<double, float, false>, cs);
         } else if (mode == VTX_F32)
             hipLaunchKernelGGL((k_batch_relax<float, float>), grid, block, 0, cs, it, b->order_d,
                                n, b->queue, bo, b->res_d);

@@ -582,12 +582,14 @@ def _batch_case(rng, n, P0):
     return t, p
 
 
+@pytest.mark.parametrize("block_threads", [256, 512])
 @pytest.mark.parametrize("mode", ["f64", "mixed", "f32"])
-def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
+def test_batch_relax_matches_single(vtx, oracle, errlog, mode, block_threads):
     """Solid tissues (P0 < 3.8; some converge within the iteration cap, some
     do not yet) plus one fluid tissue (P0 = 3.86) that keeps cycling short
     edges and stops at max_iter: the persistent batch kernel reproduces the
-    single-tissue path exactly in every case."""
+    single-tissue path exactly in every case.  With 512 threads these
+    tissues run in the LDS-resident kernel, T1 passes included."""
     rng = np.random.default_rng(41)
     cases = [_batch_case(rng, n, P0) for n, P0 in
              ((64, 3.65), (150, 3.70), (90, 3.63), (300, 3.72), (120, 3.86))]
@@ -602,14 +604,15 @@ def test_batch_relax_matches_single(vtx, oracle, errlog, mode):
     Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
     Xs = [_dev(t.X, dt) for t, _ in cases]
     B = vtx.Batch(Ts)
-    res = B.relax(Xs, [vtx.Params.from_numpy(p, dtype=dt) for _, p in cases], mode=mode, **opts)
+    res = B.relax(Xs, [vtx.Params.from_numpy(p, dtype=dt) for _, p in cases], mode=mode,
+                  block_threads=block_threads, **opts)
     for (rs, Xs_ref, he_ref), r, X, T in zip(single, res, Xs, Ts):
         print("single", rs, "batch", r)
         assert r["status"] == rs["status"]
         assert (r["iters"], r["n_t1"], r["n_stretch"]) == (rs["iters"], rs["n_t1"], rs["n_stretch"])
         np.testing.assert_array_equal(T.topology(), he_ref)
-        errlog(f"batched vs single relaxation {mode}, {T.n_cell} cells: positions (max abs)",
-               np.abs(X.cpu().numpy() - Xs_ref).max())
+        errlog(f"batched vs single relaxation {mode}, {block_threads} threads, {T.n_cell} cells: "
+               "positions (max abs)", np.abs(X.cpu().numpy() - Xs_ref).max())
         assert np.abs(X.cpu().numpy() - Xs_ref).max() < 1e-9
         # the single path sums the line energy from FP32 lengths in MIXED mode
         assert r["energy"] == pytest.approx(
