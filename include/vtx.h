@@ -292,15 +292,16 @@ int vtx_batch_destroy(vtx_batch b);
 /* Relax every tissue of the batch (each with its own X, parameters and the
  * shared options; Methods, "Simulation engine", per tissue).  Schedules:
  *   VTX_SCHED_PERSISTENT  one persistent launch captured in a graph, one
- *                         workgroup of `block_threads` (256, 512 or 1024)
- *                         threads per tissue looping the whole relaxation,
- *                         tissues taken from a device work queue in
- *                         descending size; with T1 off and 512 threads, a
- *                         batch whose tissues all have at most 1024 cells
- *                         and fit the per-workgroup LDS (both position
- *                         buffers, cell coefficients, corner rows) runs a
- *                         kernel that keeps them there and the vertex stars
- *                         in registers;
+ *                         workgroup of `block_threads` (256, 512 or 1024;
+ *                         0 chooses) threads per tissue looping the whole
+ *                         relaxation, tissues taken from a device work
+ *                         queue in descending size.  With 512 threads (or
+ *                         0), a batch whose tissues all have at most 1024
+ *                         cells and fit the per-workgroup LDS (both
+ *                         position buffers, cell coefficients, corner rows)
+ *                         runs a kernel that keeps them there and the vertex
+ *                         stars in registers, T1 passes included; 0 takes
+ *                         1024 threads otherwise;
  *   VTX_SCHED_GRID        each tissue in turn through vtx_relax (all
  *                         workgroups of the GPU on one tissue; suits a few
  *                         large tissues); block_threads is ignored;

@@ -1413,8 +1413,9 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
         return VTX_OK;
     }
     if (schedule != VTX_SCHED_PERSISTENT) return set_error(VTX_E_ARG, "unknown schedule");
-    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
-        return set_error(VTX_E_ARG, "block_threads must be 256, 512 or 1024");
+    if (block_threads != 0 && block_threads != 256 && block_threads != 512 &&
+        block_threads != 1024)
+        return set_error(VTX_E_ARG, "block_threads must be 0, 256, 512 or 1024");
     return batch_relax_run(b, mode, X, p, o, nullptr, nullptr, 0.0, block_threads, res,
                            (hipStream_t)stream);
 }

@@ -45,7 +45,7 @@ def fit_logistic(p0, frac):
 
 def rigidity_sweep(p0_grid=None, n_per_p0=100, n_cell=100, seed=601, e_tol=1e-6,
                    eta=1e-2, tol=1e-6, max_iter=300000, l_min=0.01, mode="mixed",
-                   block_threads=256, log=print):
+                   block_threads=0, log=print):
     if p0_grid is None:
         p0_grid = np.round(np.linspace(3.6, 4.1, 11), 4)
     rng = np.random.default_rng(seed)

@@ -399,11 +399,13 @@ class Batch:
         xs = (C.c_void_p * n)(*[X.data_ptr() for X in Xs])
         return xs, cps, keep
 
-    def relax(self, Xs, params_list, mode="mixed", schedule=SCHED_PERSISTENT, block_threads=256,
+    def relax(self, Xs, params_list, mode="mixed", schedule=SCHED_PERSISTENT, block_threads=0,
               **opts):
         """schedule: SCHED_PERSISTENT (one workgroup of `block_threads` per
-        tissue), SCHED_GRID (each tissue in turn on the whole GPU) or
-        SCHED_AUTO (timed trials pick one)."""
+        tissue: 256, 512 or 1024, or 0 to let the library choose, which takes
+        the LDS-resident kernel when every tissue fits it), SCHED_GRID (each
+        tissue in turn on the whole GPU) or SCHED_AUTO (timed trials pick
+        one)."""
         m = _mode(mode)
         xs, cps, keep = self._marshal(Xs, params_list, m)
         o = relax_opts(**opts)
