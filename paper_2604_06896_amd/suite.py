@@ -247,3 +247,41 @@ def param_gradients(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000, 
                           "directions_per_full_gradient": Ts[0].n_edge,
                           "vs_adjoint_max_rel_diff": max(errs)}
     return out
+
+
+def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000,
+                         log=print):
+    """The inverse workload's batched adjoint on its own: targets and
+    predictions relaxed (batched, FP64, T1), then one batched adjoint
+    launch (CG to 1e-8).  A short program for kernel counters."""
+    work = g.workload_inverse(seed=seed, n_tissue=n_tissue, n_cell=n_cell)
+    Ts_t = [V.Tissue.from_tissue(t) for t, _, _ in work]
+    Ts = [V.Tissue.from_tissue(t) for t, _, _ in work]
+
+    def prm(p):
+        return V.Params(KA=1.0, A0=1.0, KP=1.0, P0=3.75,
+                        lam=torch.as_tensor(p.lam, dtype=torch.float64, device="cuda"))
+    ropts = dict(eta=3e-3, tol=1e-6, max_iter=relax_max_iter, t1_enable=True, l_min=0.01)
+    Xt = [torch.as_tensor(t.X, dtype=torch.float64, device="cuda") for t, _, _ in work]
+    Xs = [torch.as_tensor(t.X, dtype=torch.float64, device="cuda") for t, _, _ in work]
+    V.Batch(Ts_t).relax(Xt, [prm(ps) for _, ps, _ in work], mode="f64", **ropts)
+    Pi = [prm(pi) for _, _, pi in work]
+    V.Batch(Ts).relax(Xs, Pi, mode="f64", **ropts)
+    b = [T.v2v(X, Y)[1] for T, X, Y in zip(Ts, Xs, Xt)]
+    _sync()
+    t0 = time.perf_counter()
+    _, info = V.Batch(Ts).param_grad(Xs, Pi, dC_dX=b, cg_tol=1e-8, cg_max_iter=100000)
+    _sync()
+    dt = time.perf_counter() - t0
+    it = [i["cg_iters"] for i in info]
+    log(f"batched adjoint: {n_tissue} tissues in {dt * 1e3:.2f} ms, CG steps median "
+        f"{int(np.median(it))} max {max(it)}")
+    return dt
+
+
+if __name__ == "__main__":
+    import sys
+    if sys.argv[1:] == ["adjoint"]:
+        batched_adjoint_once()
+    else:
+        raise SystemExit("usage: python -m paper_2604_06896_amd.suite adjoint")
