@@ -280,8 +280,12 @@ def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000
 
 
 if __name__ == "__main__":
+    # short programs for kernel counters: the batched adjoint of the inverse
+    # workload, or the 512-tissue batched relaxation capped at 2e4 iterations
     import sys
     if sys.argv[1:] == ["adjoint"]:
         batched_adjoint_once()
+    elif sys.argv[1:] == ["relax"]:
+        batched_relax(max_iter=20000, plain_sample=0, block_threads=1024)
     else:
-        raise SystemExit("usage: python -m paper_2604_06896_amd.suite adjoint")
+        raise SystemExit("usage: python -m paper_2604_06896_amd.suite adjoint|relax")
