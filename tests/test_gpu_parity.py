@@ -767,6 +767,37 @@ def test_batch_adjoint_matches_single_and_oracle(vtx, oracle, errlog, small_equi
            "(max |dg| / max |g|, worst tissue)", worst)
 
 
+@pytest.mark.parametrize("block_threads", [1024, 512])
+@pytest.mark.parametrize("mode", ["mixed", "f32"])
+def test_batch_adjoint_reduced_precision(vtx, errlog, small_equilibria, mode, block_threads):
+    """The batched adjoint in MIXED and FP32 (FP32 Hessian products, FP64
+    dots), in the general loop (1024 threads) and the register-resident form
+    (512), equals the single-tissue solve in the same precision, and stays
+    within that precision of the FP64 gradient."""
+    dt = vtx.pos_dtype(mode)
+    Ts, Xs, Ps, bs, singles, refs = [], [], [], [], [], []
+    for t, m, X, p, Xt in small_equilibria:
+        T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+        b = _dev(np.random.default_rng(7).normal(size=X.shape))
+        g64, _ = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=b, cg_tol=1e-10)
+        P = vtx.Params.from_numpy(p, dtype=dt)
+        gs, info = T.param_grad(_dev(X, dt), P, dC_dX=b, mode=mode, cg_tol=1e-5)
+        assert info["status"] == 0, info
+        Ts.append(T); Xs.append(_dev(X, dt)); Ps.append(P); bs.append(b)
+        singles.append((gs.cpu().numpy(), info)); refs.append(g64.cpu().numpy())
+    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, mode=mode, cg_tol=1e-5,
+                                           block_threads=block_threads)
+    worst = 0.0
+    for (gs, info), g64, gb, inf in zip(singles, refs, outs, infos):
+        assert inf["status"] == 0, inf
+        gb = gb.cpu().numpy()
+        assert np.abs(gb - gs).max() < 1e-4 * np.abs(gs).max()
+        worst = max(worst, np.abs(gb - g64).max() / np.abs(g64).max())
+        assert np.abs(gb - g64).max() < 1e-3 * np.abs(g64).max()
+    errlog(f"batched adjoint {mode}, {block_threads} threads, CG to 1e-5: against the FP64 "
+           "gradient (max |dg| / max |g|, worst tissue)", worst)
+
+
 @pytest.mark.parametrize("block_threads", [1024, 512, 256])
 def test_batch_adjoint_lds_and_global_paths(vtx, block_threads):
     """One batch holding tissues whose Hessian-product arrays fit in the
