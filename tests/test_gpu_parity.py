@@ -575,6 +575,41 @@ def test_inverse_workload_full_size_gradients(vtx, oracle, errlog):
 
 # ------------------------------------------------------------------- batched
 
+def test_batched_relax_full_size_512_tissues(vtx, oracle, errlog):
+    """The 512-tissue workload at full size (64-4096 cells per tissue) in the
+    benchmark's launch configuration (one persistent launch, a 1024-thread
+    workgroup per tissue, T1 on), capped at 300 iterations and in FP64: the
+    smallest, a median and the largest tissue of the batch equal the
+    oracle's relaxation of the same tissue, topology bit-exact.  (The
+    benchmark's MIXED run differs from FP64 by FP32 force rounding, which can
+    move a T1 decision at the threshold, so it is compared at the force level
+    elsewhere.)"""
+    work = g.workload_batch()
+    assert len(work) == 512
+    sizes = np.array([t.n_cell for t, _ in work])
+    picks = [int(sizes.argmin()), int(np.argsort(sizes)[len(sizes) // 2]), int(sizes.argmax())]
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=300, t1_enable=True, l_min=0.01)
+    Ts = [vtx.Tissue.from_tissue(t) for t, _ in work]
+    Xs = [_dev(t.X) for t, _ in work]
+    Ps = [vtx.Params.from_numpy(p) for _, p in work]
+    res = vtx.Batch(Ts).relax(Xs, Ps, mode="f64", block_threads=1024, **opts)
+    assert all(r["iters"] == 300 or r["status"] == 0 for r in res)
+    for i in picks:
+        t, p = work[i]
+        m = oracle.Mesh.from_tissue(t)
+        X = t.X.copy()
+        ro = oracle.relax(m, X, p, patience=1, **opts)
+        r = res[i]
+        assert (r["iters"], r["n_t1"], r["n_stretch"], r["status"]) == (
+            ro["iters"], ro["n_t1"], ro["n_stretch"], ro["status"])
+        np.testing.assert_array_equal(Ts[i].topology(), m.he)
+        d = np.abs(Xs[i].cpu().numpy() - X).max()
+        errlog(f"batched relaxation, 512-tissue workload, {t.n_cell}-cell tissue, 300 FP64 "
+               "steps with T1: positions against the oracle (max abs)", d)
+        assert d < 1e-9
+        assert r["energy"] == pytest.approx(ro["energy"], rel=1e-10)
+
+
 def _batch_case(rng, n, P0):
     t = g.random_tissue(n, np.sqrt(n), rng=rng)
     p = g.uniform_params(t, P0=P0)
