@@ -575,6 +575,38 @@ def test_inverse_workload_full_size_gradients(vtx, oracle, errlog):
 
 # ------------------------------------------------------------------- batched
 
+def test_batched_adjoint_full_size_64_tissues(vtx, oracle, errlog):
+    """The inverse workload at full size (64 tissues of 1000 cells): targets
+    and predictions relaxed in one batch each (FP64, T1), then the batched
+    adjoint in the benchmark's configuration (the library's choice, the
+    register-resident CG at 512 threads; CG to 1e-8); two sampled tissues
+    against the oracle's adjoint at the same state and topology."""
+    work = g.workload_inverse()
+    assert len(work) == 64
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=2000000, t1_enable=True, l_min=0.01)
+    Tt = [vtx.Tissue.from_tissue(t) for t, _, _ in work]
+    T = [vtx.Tissue.from_tissue(t) for t, _, _ in work]
+    Xt = [_dev(t.X) for t, _, _ in work]
+    X = [_dev(t.X) for t, _, _ in work]
+    P = [vtx.Params.from_numpy(pi) for _, _, pi in work]
+    rt = vtx.Batch(Tt).relax(Xt, [vtx.Params.from_numpy(ps) for _, ps, _ in work], mode="f64",
+                             **opts)
+    r = vtx.Batch(T).relax(X, P, mode="f64", **opts)
+    assert all(x["status"] == 0 for x in rt + r)
+    b = [Ti.v2v(Xi, Yi)[1] for Ti, Xi, Yi in zip(T, X, Xt)]
+    grads, infos = vtx.Batch(T).param_grad(X, P, dC_dX=b, cg_tol=1e-8)
+    assert all(i["status"] == 0 for i in infos)
+    for k in (0, 37):
+        t, _, pi = work[k]
+        m = oracle.Mesh(T[k].topology(), t.n_vert, t.Lx, t.Ly)
+        go, info_o = oracle.adjoint_grad(m, X[k].cpu().numpy(), pi, b[k].cpu().numpy(), tol=1e-8)
+        assert info_o["status"] == 0
+        err = np.abs(grads[k].cpu().numpy() - go).max() / np.abs(go).max()
+        errlog(f"batched adjoint f64, inverse workload at full size, tissue {k} (max |dg| / "
+               "max |g|)", err)
+        assert err < 1e-6
+
+
 def test_batched_relax_full_size_512_tissues(vtx, oracle, errlog):
     """The 512-tissue workload at full size (64-4096 cells per tissue) in the
     benchmark's launch configuration (one persistent launch, a 1024-thread
