@@ -64,7 +64,7 @@ struct DevTissue {
     int32_t *star_he;    // [3][n_vert] outgoing half-edges, counter-clockwise
 };
 
-__host__ __device__ inline int64_t star_nb_at(int64_t n, int k, int64_t v) { return 4 * v + k; }
+__host__ __device__ inline int64_t star_nb_at(int64_t /*n*/, int k, int64_t v) { return 4 * v + k; }
 __host__ __device__ inline int64_t star_cell_at(int64_t n, int k, int64_t v) {
     return k == 0 ? 4 * v + 3 : 4 * n + 4 * v + (k - 1);
 }
