@@ -125,6 +125,21 @@ __device__ __forceinline__ double bsum_bcast(double v, double *sh, double *bc) {
     return out;
 }
 
+// Block-wide sum returned to every thread: the wave sums go to LDS and every
+// thread adds them in wave order, so the result equals block_sum's (thread
+// 0's) in all threads without a broadcast round.
+__device__ __forceinline__ double block_allsum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();  // `sh` may still be read by the previous reduction
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) r += sh[w];
+    return r;
+}
+
 // LDS bytes the batched adjoint needs to hold, for one tissue, the arrays its
 // Hessian-vector product gathers: positions, the vector multiplied, and the
 // two per-cell coefficient pairs (cA, cP at X* and G, B of the vector).
@@ -191,8 +206,8 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
                                              const GradItem &G, unsigned char *lds,
                                              int64_t o_q, int64_t o_c, int64_t o_a,
                                              int64_t o_r, double mbx, double mby,
-                                             const GradOpts &o, double *sh, double *s_bc,
-                                             int *s_scan, int64_t &it_out, double &rel_out) {
+                                             const GradOpts &o, double *sh, int *s_scan,
+                                             int64_t &it_out, double &rel_out) {
     constexpr int KV = 2 * K;
     const int tid = threadIdx.x, bd = blockDim.x, nv = t.n_vert;
     const PosT *Xl = (const PosT *)lds;
@@ -251,7 +266,7 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
             rr += r0 * r0 + r1 * r1;
         }
     }
-    rr = bsum_bcast(rr, sh, s_bc);  // its barriers also publish q and the rows
+    rr = block_allsum(rr, sh);  // its barriers also publish q and the rows
     const double rr0 = rr;
     int status = rr0 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
     int64_t it = 0;
@@ -288,7 +303,7 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
                 d += hvp_vertex_star<PosT, M>(t, L, auxl, ql, v, aq[j][0], aq[j][1]);
             }
         }
-        const double pAp = bsum_bcast(d, sh, s_bc);
+        const double pAp = block_allsum(d, sh);
         if (!(pAp > 0.0)) {
             status = VTX_CG_NEG_CURVATURE;
             break;
@@ -307,7 +322,7 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
                 rn += r0 * r0 + r1 * r1;
             }
         }
-        rn = bsum_bcast(rn, sh, s_bc);
+        rn = block_allsum(rn, sh);
         const double be = rn / rr;
         rr = rn;
         ++it;
@@ -413,8 +428,7 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
             cg_fast_fits<PosT, M, kFastK<MAXT>>(nv, t.n_cell, t.n_he, (int)blockDim.x,
                                                  lds_bytes)) {
             status = batch_cg_fast<PosT, M, (kFastK<MAXT> > 0 ? kFastK<MAXT> : 1)>(
-                t, p, G, lds_dyn, o_q, o_c, o_a, o_r, mbx, mby, o, sh, &s_bc, s_scan, it,
-                rel_res);
+                t, p, G, lds_dyn, o_q, o_c, o_a, o_r, mbx, mby, o, sh, s_scan, it, rel_res);
         } else if (!o.minres) {
             // CG: r = P b, q = r, x = 0
             double rr = 0.0;
@@ -752,7 +766,6 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
     __shared__ int s_item;
     __shared__ int s_scan[16];
     __shared__ RelaxState st;
-    __shared__ double s_mean[2];
     auto a16 = [](int64_t b) { return (b + 15) & ~(int64_t)15; };
     const M lmin2 = (M)(o.l_min * o.l_min * (1.0 + 1e-4));
     for (;;) {
@@ -901,15 +914,8 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                         sy += cy;
                     }
                 }
-                const double bx = block_sum(sx, sh);
-                const double by = block_sum(sy, sh);
-                if (tid == 0) {
-                    s_mean[0] = bx * inv_n;
-                    s_mean[1] = by * inv_n;
-                }
-                __syncthreads();
-                mx = s_mean[0];
-                my = s_mean[1];
+                mx = block_allsum(sx, sh) * inv_n;
+                my = block_allsum(sy, sh) * inv_n;
             }
             // vertex pass with the step
             double mf = 0.0;
