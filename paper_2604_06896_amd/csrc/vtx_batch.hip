@@ -114,17 +114,6 @@ __device__ __forceinline__ void nudge_grad(const BatchItem &B, const PosT *X, in
 
 __global__ void k_reset_queue(unsigned int *q) { *q = 0u; }
 
-// Block-wide sum over a strided set, fixed order (thread 0 has the result,
-// broadcast through `bc`).
-__device__ __forceinline__ double bsum_bcast(double v, double *sh, double *bc) {
-    const double r = block_sum(v, sh);
-    if (threadIdx.x == 0) *bc = r;
-    __syncthreads();
-    const double out = *bc;
-    __syncthreads();
-    return out;
-}
-
 // Block-wide sum returned to every thread: the wave sums go to LDS and every
 // thread adds them in wave order, so the result equals block_sum's (thread
 // 0's) in all threads without a broadcast round.
@@ -371,7 +360,6 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                                                    vtx_grad_result *res, int lds_bytes) {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     __shared__ double sh[16];
-    __shared__ double s_bc;
     __shared__ int s_item;
     __shared__ int s_scan[16];
     for (;;) {
@@ -418,8 +406,8 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
             sx += G.b[2 * (int64_t)v];
             sy += G.b[2 * (int64_t)v + 1];
         }
-        const double mbx = bsum_bcast(sx, sh, &s_bc) / (double)nv;
-        const double mby = bsum_bcast(sy, sh, &s_bc) / (double)nv;
+        const double mbx = block_allsum(sx, sh) / (double)nv;
+        const double mby = block_allsum(sy, sh) / (double)nv;
         int status;
         int64_t it = 0;
         double rel_res;
@@ -442,7 +430,7 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                 x[2 * (int64_t)v + 1] = 0.0;
                 rr += r0 * r0 + r1 * r1;
             }
-            rr = bsum_bcast(rr, sh, &s_bc);
+            rr = block_allsum(rr, sh);
             const double rr0 = rr;
             status = rr0 > 0.0 ? VTX_CG_MAXITER : VTX_CONVERGED;
             while (status == VTX_CG_MAXITER && it < o.max_iter) {
@@ -456,7 +444,7 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                 double d = 0.0;
                 for (int v = threadIdx.x; v < nv; v += blockDim.x)
                     d += hvp_vertex_one<PosT, M>(t, Xh, p, cap, aux, q, Aq, v);
-                const double pAp = bsum_bcast(d, sh, &s_bc);
+                const double pAp = block_allsum(d, sh);
                 if (!(pAp > 0.0)) {
                     status = VTX_CG_NEG_CURVATURE;
                     break;
@@ -472,7 +460,7 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                     r[k + 1] = r1;
                     rn += r0 * r0 + r1 * r1;
                 }
-                rn = bsum_bcast(rn, sh, &s_bc);
+                rn = block_allsum(rn, sh);
                 const double be = rn / rr;
                 rr = rn;
                 ++it;
@@ -500,7 +488,7 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                 mq[2 * (int64_t)v + 1] = r1;
                 ss += r0 * r0 + r1 * r1;
             }
-            const double beta1 = sqrt(bsum_bcast(ss, sh, &s_bc));
+            const double beta1 = sqrt(block_allsum(ss, sh));
             const double inv1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
             for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
                 mq[k] *= inv1;
@@ -516,14 +504,14 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
                 double d = 0.0;
                 for (int v = threadIdx.x; v < nv; v += blockDim.x)
                     d += hvp_vertex_one<PosT, M>(t, Xh, p, cap, aux, mq, mz, v);
-                const double alpha = bsum_bcast(d, sh, &s_bc);
+                const double alpha = block_allsum(d, sh);
                 double zz = 0.0;
                 for (int k = threadIdx.x; k < 2 * nv; k += blockDim.x) {
                     const double zk = mz[k] - (alpha * mq[k] + beta * mqp[k]);
                     mz[k] = zk;
                     zz += zk * zk;
                 }
-                const double beta_next = sqrt(bsum_bcast(zz, sh, &s_bc));
+                const double beta_next = sqrt(block_allsum(zz, sh));
                 const double eps = s2 * beta, dbar = c2 * beta;
                 const double delta = c1 * dbar + s1 * alpha;
                 const double gbar = -s1 * dbar + c1 * alpha;
@@ -563,8 +551,8 @@ __global__ __launch_bounds__(MAXT) void k_batch_cg(const GradItem *__restrict__ 
             sx += x[2 * (int64_t)v];
             sy += x[2 * (int64_t)v + 1];
         }
-        const double mxx = bsum_bcast(sx, sh, &s_bc) / (double)nv;
-        const double mxy = bsum_bcast(sy, sh, &s_bc) / (double)nv;
+        const double mxx = block_allsum(sx, sh) / (double)nv;
+        const double mxy = block_allsum(sy, sh) / (double)nv;
         for (int v = threadIdx.x; v < nv; v += blockDim.x) {
             x[2 * (int64_t)v] -= mxx;
             x[2 * (int64_t)v + 1] -= mxy;
