@@ -312,7 +312,8 @@ int relax_impl(vtx_tissue t, int mode, void *X, const vtx_params *p, const vtx_r
     // energy (and nudge energy) at the returned positions
     launch_eval(t->d, t->w, mode, X, raw(p), t->w.scal + 4, nullptr, nullptr, s);
     if (ra.nudge == 1) launch_v2v(t->d, t->w, mode, X, o->X_target, t->w.scal + 5, nullptr, s);
-    if (ra.nudge == 2) launch_dot_pos(t->w, VTX_F64, (int)t->n_vert, o->g_lin, X, t->w.scal + 5, s);
+    if (ra.nudge == 2)
+        launch_dot_pos(t->w, mode, (int)t->n_vert, (const double *)o->g_lin, X, t->w.scal + 5, s);
     if ((rc = check_launch("final energy"))) return rc;
     double e[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(e, t->w.scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -636,9 +636,10 @@ __global__ __launch_bounds__(kBlock) void k_v2v(DevTissue t, const PosT *X, cons
     }
 }
 
-// g . X (linear nudge energy)
+// g . X: the linear nudge energy (g the double cost gradient, X the
+// positions in their own precision) or a dot product of two double fields
 template <typename PosT>
-__global__ __launch_bounds__(kBlock) void k_dot_pos(const PosT *g, const PosT *X, int nv,
+__global__ __launch_bounds__(kBlock) void k_dot_pos(const double *g, const PosT *X, int nv,
                                                     double *part, LoopCtl *ctl, double *out) {
     __shared__ double sh[kBlock / 64];
     double c = 0.0;
@@ -1155,15 +1156,15 @@ void launch_sens_rhs(const DevTissue &t, const Workspace &w, const void *X, cons
                        theta == VTX_THETA_LAMBDA ? 1.0 : -1.0, rhs);
 }
 
-void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const void *X,
+void launch_dot_pos(const Workspace &w, int mode, int nv, const double *g, const void *X,
                     double *out, hipStream_t s) {
     const unsigned gv0 = blocks_for(nv);
     const unsigned gv = gv0 < (unsigned)kRedBlocks ? gv0 : (unsigned)kRedBlocks;
     if (mode == VTX_F32)
-        hipLaunchKernelGGL((k_dot_pos<float>), dim3(gv), dim3(kBlock), 0, s, (const float *)g,
+        hipLaunchKernelGGL((k_dot_pos<float>), dim3(gv), dim3(kBlock), 0, s, g,
                            (const float *)X, nv, w.partials2, w.ctl + 1, out);
     else
-        hipLaunchKernelGGL((k_dot_pos<double>), dim3(gv), dim3(kBlock), 0, s, (const double *)g,
+        hipLaunchKernelGGL((k_dot_pos<double>), dim3(gv), dim3(kBlock), 0, s, g,
                            (const double *)X, nv, w.partials2, w.ctl + 1, out);
 }
 

@@ -55,7 +55,7 @@ void launch_cell_exact(const DevTissue &t, int mode, const void *X, double *A, d
                        hipStream_t s);
 void launch_v2v(const DevTissue &t, const Workspace &w, int mode, const void *X, const void *Xt,
                 double *C, double *grad, hipStream_t s);
-void launch_dot_pos(const Workspace &w, int mode, int nv, const void *g, const void *X,
+void launch_dot_pos(const Workspace &w, int mode, int nv, const double *g, const void *X,
                     double *out, hipStream_t s);
 void launch_mean_pos(const Workspace &w, int mode, int nv, const void *a, double *mean_out,
                      hipStream_t s);

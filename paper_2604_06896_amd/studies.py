@@ -90,7 +90,8 @@ def bilevel_fit(n_cell=20, seed=701, epochs=300, lr=1e-3, p0_mean=3.75, p0_sd=0.
     options (defaults: the paper's benchmark settings, eta 1e-2, at most 1e3
     iterations, tolerance 1e-3, patience 10, T1 below 5e-3), warm-started at
     the previous equilibrium.  Outer cost: v2v to the target vertices.
-    Returns per-epoch cost, mean relative L1 error and Pearson correlation."""
+    Returns per-epoch cost, mean relative L1 error and Pearson correlation,
+    and theta before the first and after every epoch."""
     rng = np.random.default_rng(seed)
     t = g.random_tissue(n_cell, float(np.sqrt(n_cell)), rng=rng)
     theta_star = rng.normal(p0_mean, p0_sd, n_cell)
@@ -116,7 +117,7 @@ def bilevel_fit(n_cell=20, seed=701, epochs=300, lr=1e-3, p0_mean=3.75, p0_sd=0.
     nv = t.n_vert
     Lbox = torch.tensor([t.Lx, t.Ly], dtype=torch.float64, device=dev)
     ts = torch.as_tensor(theta_star, dtype=torch.float64, device=dev)
-    hist = {"cost": [], "rel_l1": [], "pearson": []}
+    hist = {"cost": [], "rel_l1": [], "pearson": [], "theta": [theta0.copy()]}
     for k in range(epochs):
         opt.zero_grad()
         Xs = equilibrium(theta, X, T, base, which="P0", mode="f64", relax=inner, grad=grad)
@@ -134,6 +135,7 @@ def bilevel_fit(n_cell=20, seed=701, epochs=300, lr=1e-3, p0_mean=3.75, p0_sd=0.
         hist["cost"].append(cost.item())
         hist["rel_l1"].append(rel)
         hist["pearson"].append(r)
+        hist["theta"].append(theta.detach().cpu().numpy().copy())
         if log and (k % max(1, epochs // 10) == 0 or k == epochs - 1):
             log(f"bilevel fit [{method}] epoch {k}: cost {cost.item():.3e}, "
                 f"rel L1 {rel:.4f}, Pearson {r:.3f}")
