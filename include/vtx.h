@@ -188,6 +188,20 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he);
 int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
                       double *E_dev, void *F, double *maxf_dev, void *stream);
 
+/* vtx_energy_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with their scratch (per-cell
+ * coefficients, per-block partial sums, control blocks) in a fixed device
+ * array of the library (about 2.1 MiB, held on every GPU the library runs
+ * on until the process ends) instead of the tissue's workspace.  Allocates
+ * nothing and issues no memset (a small kernel clears the control blocks).
+ * Limits: at most 131072 cells and 262144 vertices, else VTX_E_CAPACITY.
+ * All calls on one GPU share that array, so calls that overlap on one GPU
+ * (different streams, threads or tissues) race; serialise them.  Arguments,
+ * outputs and errors as vtx_energy_forces.  Asynchronous. */
+int vtx_energy_forces_noalloc(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                              double *E_dev, void *F, double *maxf_dev, void *stream);
+
 /* Cell pass alone: per-cell coefficients (cA, cP) = (2 K_A (A - A0),
  * 2 K_P (P - P0)) at X, i.e. minus the cell pressure and the cortical
  * tension of each cell (derivatives of E with respect to A and P; Methods,

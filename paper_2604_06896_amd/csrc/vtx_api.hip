@@ -8,12 +8,41 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "vtx_launch.h"
 
 using namespace vtx;
+
+// ------------------------------------------------- allocation-free scratch
+// Fixed device scratch of vtx_energy_forces_noalloc: the per-cell
+// coefficients, the per-block partial sums and two loop control blocks of
+// one evaluation, for tissues of up to kNoAllocCells cells and
+// kNoAllocVerts vertices.  Every GPU the library runs on holds one copy
+// until the process ends.  In host code `scratch` names a host-side stand-in;
+// its device address comes from hipGetSymbolAddress (noalloc_scratch).
+namespace {
+constexpr int64_t kNoAllocCells = 1 << 17;
+constexpr int64_t kNoAllocVerts = 1 << 18;
+constexpr size_t kNoAllocCapBytes = 16 * (size_t)kNoAllocCells;
+constexpr size_t kNoAllocPartBytes = 8 * (size_t)((kNoAllocCells + kBlock - 1) / kBlock);
+constexpr size_t kNoAllocMpartBytes = 16 * (size_t)((kNoAllocVerts + kBlock - 1) / kBlock);
+constexpr size_t kNoAllocCtlOffset =
+    (kNoAllocCapBytes + kNoAllocPartBytes + kNoAllocMpartBytes + 255) & ~(size_t)255;
+constexpr size_t kNoAllocBytes = kNoAllocCtlOffset + ((2 * sizeof(LoopCtl) + 255) & ~(size_t)255);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Clears the two control blocks in the scratch (a kernel, not a memset, so a
+// caller may capture the call in a graph).
+__global__ void k_clear_ctl(LoopCtl *ctl) {
+    const int n = (int)(2 * sizeof(LoopCtl) / sizeof(uint32_t));
+    uint32_t *w = reinterpret_cast<uint32_t *>(ctl);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = 0u;
+}
 
 struct vtx_tissue_s {
     DevTissue d;
@@ -482,6 +511,59 @@ int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_param
     if (!t || !X || !p || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
     launch_eval(t->d, t->w, mode, X, raw(p), E_dev, F, maxf_dev, (hipStream_t)stream);
     return check_launch("vtx_energy_forces");
+}
+
+}  // extern "C"
+
+namespace {
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; NULL on failure.
+unsigned char *noalloc_scratch(int *err) {
+    static std::mutex mu;
+    static unsigned char *addr[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) {
+        *err = fail(VTX_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *err = fail(VTX_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        addr[dev] = (unsigned char *)ptr;
+    }
+    return addr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int vtx_energy_forces_noalloc(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
+                              double *E_dev, void *F, double *maxf_dev, void *stream) {
+    if (!t || !X || !p || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
+    if (t->n_cell > kNoAllocCells || t->n_vert > kNoAllocVerts)
+        return fail(VTX_E_CAPACITY,
+                    "vtx_energy_forces_noalloc: %lld cells / %lld vertices exceed its fixed "
+                    "scratch (at most %lld cells and %lld vertices)",
+                    (long long)t->n_cell, (long long)t->n_vert, (long long)kNoAllocCells,
+                    (long long)kNoAllocVerts);
+    int rc = VTX_OK;
+    unsigned char *base = noalloc_scratch(&rc);
+    if (!base) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace w{};
+    w.cap = (double *)base;
+    w.partials = (double *)(base + kNoAllocCapBytes);
+    w.mpart = (double *)(base + kNoAllocCapBytes + kNoAllocPartBytes);
+    w.ctl = (LoopCtl *)(base + kNoAllocCtlOffset);
+    hipLaunchKernelGGL(k_clear_ctl, dim3(1), dim3(64), 0, s, w.ctl);
+    launch_eval(t->d, w, mode, X, raw(p), E_dev, F, maxf_dev, s);
+    return check_launch("vtx_energy_forces_noalloc");
 }
 
 int vtx_cell_coeffs(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,

@@ -87,6 +87,7 @@ def lib():
         L.vtx_tissue_get_topology.argtypes = [vp, vp]
         L.vtx_tissue_set_topology.argtypes = [vp, vp]
         L.vtx_energy_forces.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
+        L.vtx_energy_forces_noalloc.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
         L.vtx_cell_coeffs.argtypes = [vp, i32, vp, P(_Params), vp, vp]
         L.vtx_vertex_forces.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
         L.vtx_cell_geometry.argtypes = [vp, i32, vp, vp, vp, vp]
