@@ -27,20 +27,27 @@ from .autograd import equilibrium
 
 
 def _logistic(x, pc, w):
-    return 1.0 / (1.0 + np.exp(-(x - pc) / w))
+    from scipy.special import expit
+    return expit((np.asarray(x, dtype=np.float64) - pc) / w)
 
 
 def fit_logistic(p0, frac):
-    """Least-squares logistic fit (p_c, w) to fractions in [0, 1]."""
-    from scipy.optimize import curve_fit
+    """Least-squares logistic fit (p_c, w) to fractions in [0, 1], with p_c
+    inside the sampled range and the width between 1e-3 and the range (a
+    step between two grid points then fits at the smallest width instead
+    of running off to zero)."""
+    from scipy.optimize import least_squares
     p0 = np.asarray(p0, dtype=np.float64)
     frac = np.asarray(frac, dtype=np.float64)
+    lo, hi = float(p0.min()), float(p0.max())
+    span = max(hi - lo, 1e-3)
     k = int(np.argmin(np.abs(frac - 0.5)))
-    try:
-        (pc, w), _ = curve_fit(_logistic, p0, frac, p0=(p0[k], 0.02), maxfev=20000)
-    except RuntimeError:
+    r = least_squares(lambda q: _logistic(p0, q[0], q[1]) - frac,
+                      x0=(min(max(p0[k], lo), hi), min(0.02, span)),
+                      bounds=([lo, 1e-3], [hi, span]), method="trf")
+    if not r.success:
         return float("nan"), float("nan")
-    return float(pc), float(abs(w))
+    return float(r.x[0]), float(r.x[1])
 
 
 def rigidity_sweep(p0_grid=None, n_per_p0=100, n_cell=100, seed=601, e_tol=1e-6,
@@ -52,7 +59,7 @@ def rigidity_sweep(p0_grid=None, n_per_p0=100, n_cell=100, seed=601, e_tol=1e-6,
     L = float(np.sqrt(n_cell))
     dt = V.pos_dtype(mode)
     out = {"p0": [], "fraction_zero_energy": [], "energy_per_cell_median": [],
-           "converged": [], "batch_s": []}
+           "converged": [], "batch_s": [], "energy_per_cell": []}
     for p0 in p0_grid:
         ts = [g.random_tissue(n_cell, L, rng=rng) for _ in range(n_per_p0)]
         Ts = [V.Tissue.from_tissue(t) for t in ts]
@@ -74,6 +81,7 @@ def rigidity_sweep(p0_grid=None, n_per_p0=100, n_cell=100, seed=601, e_tol=1e-6,
         out["energy_per_cell_median"].append(float(np.median(e)))
         out["converged"].append(conv)
         out["batch_s"].append(dtb)
+        out["energy_per_cell"].append([float(x) for x in e])
     pc, w = fit_logistic(out["p0"], out["fraction_zero_energy"])
     out["fit_p_c"], out["fit_width"] = pc, w
     log(f"rigidity sweep: logistic fit p_c = {pc:.4f}, width {w:.4f}")
