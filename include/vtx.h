@@ -84,6 +84,7 @@ extern "C" {
 #define VTX_SCHED_AUTO (-1)     /* choose by timed trials (vtx_batch_autotune)       */
 #define VTX_SCHED_PERSISTENT 0  /* one persistent launch, one workgroup per tissue   */
 #define VTX_SCHED_GRID 1        /* each tissue in turn on the whole GPU (vtx_relax)  */
+#define VTX_SCHED_SPLIT 2       /* each tissue over several cooperating workgroups   */
 
 #define VTX_GRAD_ADJOINT 0     /* implicit differentiation, adjoint form, CG */
 #define VTX_GRAD_EP_CENTRED 1  /* centred equilibrium propagation            */
@@ -319,10 +320,25 @@ int vtx_batch_destroy(vtx_batch b);
  *   VTX_SCHED_GRID        each tissue in turn through vtx_relax (all
  *                         workgroups of the GPU on one tissue; suits a few
  *                         large tissues); block_threads is ignored;
+ *   VTX_SCHED_SPLIT       T1 off only: each tissue split over K = block_threads
+ *                         (1, 2, 4 or 8; 0 chooses) cooperating 512-thread
+ *                         workgroups of one cooperative launch, each owning a
+ *                         contiguous range of vertices and the cells around
+ *                         them in LDS, with one barrier between the
+ *                         workgroups of a tissue per iteration (max |F| and
+ *                         the boundary positions); suits a few tissues of up
+ *                         to 8192 vertices.  0 takes the largest K with at
+ *                         most 64 workgroups in all and 200 vertices per
+ *                         part: a barrier between more workgroups costs
+ *                         several microseconds on this part.  A tissue one
+ *                         part cannot hold is relaxed by the persistent
+ *                         schedule instead.  Returns VTX_E_HIP if a wait
+ *                         between workgroups times out (20 s);
  *   VTX_SCHED_AUTO        vtx_batch_autotune first, then its choice.
- * Every schedule gives the same results as vtx_relax on each tissue.  X and
- * p are host arrays of n entries (device pointers inside).  Results go to
- * the host array res[n]; synchronises.  Nudges are not supported here. */
+ * Every schedule gives the same iterates as vtx_relax on each tissue (the
+ * reported energy is summed in another order by the split schedule).  X
+ * and p are host arrays of n entries (device pointers inside).  Results go
+ * to the host array res[n]; synchronises.  Nudges are not supported here. */
 int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
                     const vtx_relax_opts *o, int32_t schedule, int32_t block_threads,
                     vtx_relax_result *res, void *stream);
@@ -330,11 +346,13 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
 /* Choose the schedule of vtx_batch_relax for this batch, mode, X, p and o
  * from timed trials on copies of the positions (T1 off, `trial_iters`
  * iterations, no convergence test): the persistent schedule with 256, 512
- * and 1024 threads on all tissues, and the grid schedule on the (up to) two
- * largest tissues, extrapolated to the batch.  X is not modified; the trial
- * buffers are allocated and freed here.  Writes the choice to *schedule and
- * *block_threads and, if trial_ms is not NULL, the four projected times in
- * milliseconds (persistent 256, 512, 1024, grid).  Synchronises. */
+ * and 1024 threads on all tissues, the grid schedule on the (up to) two
+ * largest tissues, extrapolated to the batch, and, when o has T1 off, the
+ * split schedule with 2, 4 and 8 workgroups per tissue.  X is not
+ * modified; the trial buffers are allocated and freed here.  Writes the
+ * choice to *schedule and *block_threads and, if trial_ms is not NULL, the
+ * seven projected times in milliseconds (persistent 256, 512, 1024, grid,
+ * split 2, 4, 8; -1 for a split trial not run).  Synchronises. */
 int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_params *p,
                        const vtx_relax_opts *o, int32_t trial_iters, int32_t *schedule,
                        int32_t *block_threads, double *trial_ms, void *stream);
@@ -351,11 +369,21 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
  * has that form, else 1024.  EP_CENTRED / EP_FORWARD: batched nudged
  * relaxations (vtx_batch_relax with a per-tissue nudge, workgroups of
  * `block_threads`; 0 takes the LDS-resident relaxation of vtx_batch_relax
- * when every tissue fits it, else 1024 threads) and one estimate launch.  X_star, p, dC_dX, X_target
+ * when every tissue fits it, else 1024 threads) and one estimate launch.
+ * block_threads = -K (K = 1, 2, 4 or 8) splits each tissue over K
+ * cooperating 512-thread workgroups of one cooperative launch instead: for
+ * ADJOINT (FP64 only) each part keeps the constant geometry of the
+ * Hessian-vector product of its vertices and cells in LDS and registers and
+ * the parts meet at two barriers per CG step; for EP the nudged relaxations
+ * take the split schedule of vtx_batch_relax.  A barrier between many
+ * workgroups costs several microseconds on this part, so splitting pays for
+ * a few tissues, not for a full device of them; a tissue one part cannot
+ * hold falls back to one workgroup.  X_star, p, dC_dX, X_target
  * and dC_dtheta are host arrays of n entries (device pointers inside; dC_dX
  * or X_target may be NULL as for vtx_param_grad).  Results go to the host
  * array res[n]; synchronises.  Errors: VTX_E_ARG (null arrays, bad mode,
- * theta, method, options or block_threads), VTX_E_HIP. */
+ * theta, method, options or block_threads), VTX_E_HIP (also: a wait between
+ * the workgroups of a split tissue timed out). */
 int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const vtx_params *p,
                          const double *const *dC_dX, const void *const *X_target,
                          const vtx_grad_opts *o, double *const *dC_dtheta, int32_t block_threads,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvtx.so")
-SOURCES = ["vtx_kernels.hip", "vtx_batch.hip", "vtx_api.hip"]
+SOURCES = ["vtx_kernels.hip", "vtx_batch.hip", "vtx_batch_mb.hip", "vtx_api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions (v_pk_*_f32)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

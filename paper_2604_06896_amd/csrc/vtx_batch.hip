@@ -11,22 +11,9 @@
 #include <string>
 #include <vector>
 
-#include "vtx_device.h"
-#include "vtx_launch.h"
+#include "vtx_batch.h"
 
 using namespace vtx;
-
-struct vtx_tissue_s;  // defined in vtx_api.hip; only its handle is used here
-
-namespace vtx {
-// Accessors implemented in vtx_api.hip.
-const DevTissue &tissue_dev(vtx_tissue t);
-const Workspace &tissue_ws(vtx_tissue t);
-int64_t tissue_size(vtx_tissue t);
-int64_t tissue_cells(vtx_tissue t);
-double *tissue_ep_buf(vtx_tissue t);
-int set_error(int code, const char *msg);
-}  // namespace vtx
 
 struct vtx_batch_s {
     std::vector<vtx_tissue> ts;
@@ -38,65 +25,12 @@ struct vtx_batch_s {
     unsigned int *queue;
     vtx_relax_result *res_d;
     vtx_grad_result *gres_d;
+    void *mb_groups;             // device MbGroup[n] (multi-workgroup adjoint)
+    int32_t *order2_d;           // device tissue list of a second launch
     hipStream_t cap_stream;
 };
 
 namespace vtx {
-
-struct BatchItem {
-    DevTissue t;
-    void *X;
-    void *xbuf;
-    void *cap;
-    int32_t *t1_list;
-    ParamsRaw p;
-    // nudge (equilibrium propagation): beta * C with C the v2v cost to Xt or
-    // the linear cost g_lin . X; the mean of grad C is removed
-    const void *Xt;
-    const double *g_lin;
-    double beta;
-};
-
-// One tissue of a batched adjoint: H mu = P b by CG, then the contraction.
-struct GradItem {
-    DevTissue t;
-    const void *X;
-    ParamsRaw p;
-    const double *b;     // dC/dX [n_vert][2]
-    double *cg;          // x, r, q, Aq: 4 x [n_vert][2]
-    void *cap;
-    void *aux;
-    double *g;           // output [n_edge] or [n_cell]
-};
-
-struct GradOpts {
-    double tol;
-    int64_t max_iter;
-    int theta;
-    int minres;  // 0: CG, 1: MINRES
-};
-
-struct BatchOpts {
-    double eta, tol, l_min, l_new;
-    int64_t patience, max_iter;
-    int t1_enable;
-};
-
-template <typename PosT>
-__device__ __forceinline__ DevParams<PosT> to_dev(const ParamsRaw &r) {
-    DevParams<PosT> p;
-    p.KA = (const PosT *)r.KA;
-    p.A0 = (const PosT *)r.A0;
-    p.KP = (const PosT *)r.KP;
-    p.P0 = (const PosT *)r.P0;
-    p.lam = (const PosT *)r.lam;
-    p.KA_s = (PosT)r.KA_s;
-    p.A0_s = (PosT)r.A0_s;
-    p.KP_s = (PosT)r.KP_s;
-    p.P0_s = (PosT)r.P0_s;
-    p.lam_s = (PosT)r.lam_s;
-    return p;
-}
 
 // Gradient of the nudge cost at vertex v (v2v, minimum image; or linear).
 template <typename PosT>
@@ -113,21 +47,6 @@ __device__ __forceinline__ void nudge_grad(const BatchItem &B, const PosT *X, in
 }
 
 __global__ void k_reset_queue(unsigned int *q) { *q = 0u; }
-
-// Block-wide sum returned to every thread: the wave sums go to LDS and every
-// thread adds them in wave order, so the result equals block_sum's (thread
-// 0's) in all threads without a broadcast round.
-__device__ __forceinline__ double block_allsum(double v, double *sh) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();  // `sh` may still be read by the previous reduction
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) r += sh[w];
-    return r;
-}
 
 // LDS bytes the batched adjoint needs to hold, for one tissue, the arrays its
 // Hessian-vector product gathers: positions, the vector multiplied, and the
@@ -155,30 +74,6 @@ __host__ __device__ inline bool cg_fast_fits(int64_t n_vert, int64_t n_cell, int
                                              int block_threads, int64_t lds_bytes) {
     return n_cell <= K * (int64_t)block_threads && n_vert <= 2 * K * (int64_t)block_threads &&
            cg_fast_lds_bytes<PosT, M>(n_vert, n_cell, n_he) <= lds_bytes;
-}
-
-// Exclusive prefix sum of one int per thread over the workgroup (up to 16
-// waves); `sh` holds 16 ints.  Also returns the total.
-__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int s = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(s, off, 64);
-        if (lane >= off) s += u;
-    }
-    if (lane == 63 || threadIdx.x == blockDim.x - 1) sh[w] = s;
-    __syncthreads();
-    int base = 0, tot = 0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 0; i < nw; ++i) {
-        const int x = sh[i];
-        if (i < w) base += x;
-        tot += x;
-    }
-    __syncthreads();
-    total = tot;
-    return base + s - v;
 }
 
 // Conjugate gradients of one tissue in which thread i owns cells i + k B
@@ -1149,8 +1044,8 @@ int run_graph(vtx_batch b, hipStream_t s, Launch launch) {
 // arrays in global memory).  Workgroups of up to 512 threads run the kernel
 // that has the register-resident CG.
 template <typename PosT, typename M, int MAXT>
-int launch_batch_cg_t(vtx_batch b, const GradItem *gi, int n, const GradOpts &go,
-                      int block_threads, hipStream_t s) {
+int launch_batch_cg_t(vtx_batch b, const GradItem *gi, const int32_t *order, int n,
+                      const GradOpts &go, int block_threads, hipStream_t s) {
     constexpr int K = kFastK<MAXT>;
     int dev = 0, lds_max = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1159,7 +1054,7 @@ int launch_batch_cg_t(vtx_batch b, const GradItem *gi, int n, const GradOpts &go
     if (e != hipSuccess) return hip_fail(e);
     const int64_t budget = (int64_t)lds_max - 1024;  // the kernel's static LDS stays below
     int64_t need = 0;
-    for (int i = 0; i < n; ++i) {
+    for (size_t i = 0; i < b->ts.size(); ++i) {
         const DevTissue &d = tissue_dev(b->ts[i]);
         int64_t nb = cg_lds_bytes<PosT, M>(d.n_vert, d.n_cell);
         if (K > 0 && !go.minres &&
@@ -1176,7 +1071,7 @@ int launch_batch_cg_t(vtx_batch b, const GradItem *gi, int n, const GradOpts &go
     }
     return run_graph(b, s, [&](hipStream_t cs) {
         hipLaunchKernelGGL((k_batch_cg<PosT, M, MAXT>), dim3(n), dim3(block_threads),
-                           (size_t)lds, cs, gi, b->order_d, n, b->queue, go, b->gres_d, lds);
+                           (size_t)lds, cs, gi, order, n, b->queue, go, b->gres_d, lds);
     });
 }
 
@@ -1201,15 +1096,50 @@ int auto_cg_threads(vtx_batch b, const GradOpts &go, int *out) {
 }
 
 template <typename PosT, typename M>
-int launch_batch_cg(vtx_batch b, const GradItem *gi, int n, const GradOpts &go,
-                    int block_threads, hipStream_t s) {
+int launch_batch_cg(vtx_batch b, const GradItem *gi, const int32_t *order, int n,
+                    const GradOpts &go, int block_threads, hipStream_t s) {
     if (block_threads == 0) {
         const int rc = auto_cg_threads<PosT, M>(b, go, &block_threads);
         if (rc) return rc;
     }
     return block_threads <= 512
-               ? launch_batch_cg_t<PosT, M, 512>(b, gi, n, go, block_threads, s)
-               : launch_batch_cg_t<PosT, M, 1024>(b, gi, n, go, block_threads, s);
+               ? launch_batch_cg_t<PosT, M, 512>(b, gi, order, n, go, block_threads, s)
+               : launch_batch_cg_t<PosT, M, 1024>(b, gi, order, n, go, block_threads, s);
+}
+
+// Plan of the multi-workgroup adjoint (FP64 CG): K parts per tissue and the
+// number of groups of the cooperative launch.  block_threads < 0 asks for
+// K = -block_threads; 0 lets the library choose: the largest K (up to 8)
+// that still gives every tissue its own group on the device at once, with
+// at least 200 vertices per part, and enough parts that no part owns more
+// than 1024 vertices.  *K = 0 when the plan does not apply.
+int plan_mb(vtx_batch b, int block_threads, int *K, int *n_groups, int *lds) {
+    *K = 0;
+    int max_blocks = 0;
+    hipError_t e = mb_capacity(&max_blocks, lds);
+    if (e != hipSuccess) return hip_fail(e);
+    const int n = (int)b->ts.size();
+    int64_t nv_min = INT64_MAX, nv_max = 0;
+    for (int i = 0; i < n; ++i) {
+        nv_min = std::min(nv_min, tissue_size(b->ts[i]));
+        nv_max = std::max(nv_max, tissue_size(b->ts[i]));
+    }
+    int k = 1;
+    if (block_threads < 0) {
+        k = -block_threads;
+        if (max_blocks < k)
+            return set_error(VTX_E_ARG, "the device cannot launch the multi-workgroup adjoint "
+                                        "cooperatively");
+    } else {
+        while (k < 8 && (int64_t)n * 2 * k <= max_blocks && nv_min / (2 * k) >= 200) k *= 2;
+        while (k < 8 && nv_max > 1024 * (int64_t)k && 2 * k <= max_blocks) k *= 2;
+        if (k < 2) return VTX_OK;
+    }
+    int g = std::min(n, max_blocks / k);
+    if (g >= 8) g -= g % 8;   // parts of a group then share an XCD (round-robin dispatch)
+    *K = k;
+    *n_groups = g;
+    return VTX_OK;
 }
 
 // Dynamic LDS for k_batch_relax_lds if every tissue of the batch fits it
@@ -1243,9 +1173,58 @@ int relax_lds_plan(vtx_batch b, int *lds) {
     return VTX_OK;
 }
 
+// The split schedule: each tissue over K cooperating workgroups
+// (k_batch_relax_mb, T1 off); tissues a part cannot hold are relaxed again
+// by the general persistent kernel.  Results to b->res_d.
+int relax_split(vtx_batch b, int mode, const BatchItem *it, const BatchOpts &bo, int n, int K,
+                hipStream_t s) {
+    int max_blocks = 0, lds = 0;
+    hipError_t e = mb_relax_capacity(mode, &max_blocks, &lds);
+    if (e != hipSuccess) return hip_fail(e);
+    if (max_blocks < K)
+        return set_error(VTX_E_ARG, "the device cannot launch the split schedule cooperatively");
+    int g = std::min(n, max_blocks / K);
+    if (g >= 8) g -= g % 8;   // parts of a group then share an XCD (round-robin dispatch)
+    // a tissue whose result is never written keeps status -1 (an error)
+    e = hipMemsetAsync(b->res_d, 0xff, sizeof(vtx_relax_result) * n, s);
+    if (e == hipSuccess)
+        e = mb_relax_launch(mode, it, b->order_d, n, bo, K, g, lds, b->res_d, b->mb_groups, s);
+    std::vector<vtx_relax_result> r(n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r.data(), b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost,
+                           s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    std::vector<int32_t> rest;
+    for (int i = 0; i < n; ++i) {
+        if (r[i].status == mb_no_fit_status()) rest.push_back(i);
+        else if (r[i].status != VTX_CONVERGED && r[i].status != VTX_NOT_CONVERGED &&
+                 r[i].status != VTX_E_NONFINITE)
+            return set_error(VTX_E_HIP, "split relaxation: a wait between the workgroups of a "
+                                        "tissue timed out");
+    }
+    if (rest.empty()) return VTX_OK;
+    e = hipMemcpyAsync(b->order2_d, rest.data(), sizeof(int32_t) * rest.size(),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    const int m = (int)rest.size();
+    return run_graph(b, s, [&](hipStream_t cs) {
+        if (mode == VTX_F32)
+            hipLaunchKernelGGL((k_batch_relax<float, float>), dim3(m), dim3(1024), 0, cs, it,
+                               b->order2_d, m, b->queue, bo, b->res_d);
+        else if (mode == VTX_F64)
+            hipLaunchKernelGGL((k_batch_relax<double, double>), dim3(m), dim3(1024), 0, cs, it,
+                               b->order2_d, m, b->queue, bo, b->res_d);
+        else
+            hipLaunchKernelGGL((k_batch_relax<double, float>), dim3(m), dim3(1024), 0, cs, it,
+                               b->order2_d, m, b->queue, bo, b->res_d);
+    });
+}
+
 int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
                     const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
-                    double beta, int block_threads, vtx_relax_result *res, hipStream_t s) {
+                    double beta, int block_threads, vtx_relax_result *res, hipStream_t s,
+                    int split_K = 0) {
     const int n = (int)b->ts.size();
     std::vector<BatchItem> items(n);
     for (int i = 0; i < n; ++i) {
@@ -1272,7 +1251,11 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     // caller asked for its workgroup size or left the choice open.
     int lds = 0;
     const bool t1 = o->t1_enable != 0;
-    if (block_threads == 0 || block_threads == kRelaxLdsThreads) {
+    if (split_K > 0 && t1) return set_error(VTX_E_ARG, "the split schedule runs without T1");
+    if (split_K > 0) {
+        const int rc = relax_split(b, mode, it, bo, n, split_K, s);
+        if (rc) return rc;
+    } else if (block_threads == 0 || block_threads == kRelaxLdsThreads) {
         int rc;
         if (mode == VTX_F32)
             rc = t1 ? relax_lds_plan<float, float, true>(b, &lds)
@@ -1290,7 +1273,7 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
         hipLaunchKernelGGL(kern, dim3(n), dim3(kRelaxLdsThreads), (size_t)lds, cs, it, b->order_d,
                            n, b->queue, bo, b->res_d);
     };
-    int rc = run_graph(b, s, [&](hipStream_t cs) {
+    int rc = split_K > 0 ? VTX_OK : run_graph(b, s, [&](hipStream_t cs) {
         const dim3 grid(n), block(block_threads);
         if (lds > 0) {
             if (mode == VTX_F32)
@@ -1334,6 +1317,20 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     return set_error(err, msg.c_str());
 }
 
+// Parts per tissue of the split schedule when the caller leaves it open:
+// the largest K (up to 8) with at most 64 workgroups in all (a barrier of
+// more concurrent workgroups costs several microseconds on this part:
+// their device-scope fences serialise per XCD) and at least 200 vertices
+// per part.
+int split_parts(vtx_batch b) {
+    const int n = (int)b->ts.size();
+    int64_t nv_min = INT64_MAX;
+    for (int i = 0; i < n; ++i) nv_min = std::min(nv_min, tissue_size(b->ts[i]));
+    int k = 1;
+    while (k < 8 && (int64_t)n * 2 * k <= 64 && nv_min / (2 * k) >= 200) k *= 2;
+    return k;
+}
+
 int check_relax_opts(const vtx_relax_opts *o) {
     if (!(o->eta > 0) || !(o->tol >= 0) || o->patience < 1 || o->max_iter < 1)
         return set_error(VTX_E_ARG, "bad relax options");
@@ -1364,6 +1361,8 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
     if (e == hipSuccess) e = hipMalloc((void **)&b->queue, sizeof(unsigned int));
     if (e == hipSuccess) e = hipMalloc((void **)&b->res_d, sizeof(vtx_relax_result) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->gres_d, sizeof(vtx_grad_result) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->mb_groups, mb_group_bytes() * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->order2_d, sizeof(int32_t) * n);
     if (e == hipSuccess)
         e = hipMemcpy(b->order_d, b->order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -1378,7 +1377,8 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
 int vtx_batch_destroy(vtx_batch b) {
     if (!b) return set_error(VTX_E_ARG, "null batch");
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {b->items, b->gitems, b->xm_list, b->order_d, b->queue, b->res_d, b->gres_d};
+    void *ptrs[] = {b->items, b->gitems, b->xm_list, b->order_d, b->queue, b->res_d, b->gres_d,
+                    b->mb_groups, b->order2_d};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1405,6 +1405,16 @@ int vtx_batch_relax(vtx_batch b, int32_t mode, void *const *X, const vtx_params 
         for (int i = 0; i < n; ++i)
             if ((rc = vtx_relax(b->ts[i], mode, X[i], &p[i], o, &res[i], stream))) return rc;
         return VTX_OK;
+    }
+    if (schedule == VTX_SCHED_SPLIT) {
+        if (o->t1_enable) return set_error(VTX_E_ARG, "the split schedule runs without T1");
+        if (block_threads != 0 && block_threads != 1 && block_threads != 2 &&
+            block_threads != 4 && block_threads != 8)
+            return set_error(VTX_E_ARG, "split schedule: block_threads (parts) must be 0, 1, 2, "
+                                        "4 or 8");
+        const int K = block_threads ? block_threads : split_parts(b);
+        return batch_relax_run(b, mode, X, p, o, nullptr, nullptr, 0.0, 0, res,
+                               (hipStream_t)stream, K);
     }
     if (schedule != VTX_SCHED_PERSISTENT) return set_error(VTX_E_ARG, "unknown schedule");
     if (block_threads != 0 && block_threads != 256 && block_threads != 512 &&
@@ -1482,6 +1492,20 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
         }
         ms[3] = t / m * n;
     }
+    // split schedule (T1 off only): 2, 4 and 8 workgroups per tissue
+    double ms_split[3] = {-1.0, -1.0, -1.0};
+    const int parts[3] = {2, 4, 8};
+    int max_blocks = 0, lds_mb = 0;
+    if (rc == VTX_OK && e == hipSuccess && !o->t1_enable)
+        e = mb_relax_capacity(mode, &max_blocks, &lds_mb);
+    for (int k = 0; k < 3 && rc == VTX_OK && e == hipSuccess && !o->t1_enable; ++k) {
+        if (max_blocks < parts[k]) break;
+        if ((e = reset()) != hipSuccess) break;
+        const auto t0 = now();
+        rc = batch_relax_run(b, mode, Xc.data(), p, &to, nullptr, nullptr, 0.0, 0, res.data(), s,
+                             parts[k]);
+        ms_split[k] = std::chrono::duration<double, std::milli>(now() - t0).count();
+    }
     (void)hipFree(buf);
     if (rc) return rc;
     if (e != hipSuccess) return hip_fail(e);
@@ -1490,8 +1514,17 @@ int vtx_batch_autotune(vtx_batch b, int32_t mode, void *const *X, const vtx_para
         if (ms[k] < ms[best]) best = k;
     *schedule = best == 3 ? VTX_SCHED_GRID : VTX_SCHED_PERSISTENT;
     *block_threads = best == 3 ? 0 : threads[best];
-    if (trial_ms)
+    double best_ms = ms[best];
+    for (int k = 0; k < 3; ++k)
+        if (ms_split[k] >= 0.0 && ms_split[k] < best_ms) {
+            best_ms = ms_split[k];
+            *schedule = VTX_SCHED_SPLIT;
+            *block_threads = parts[k];
+        }
+    if (trial_ms) {
         for (int k = 0; k < 4; ++k) trial_ms[k] = ms[k];
+        for (int k = 0; k < 3; ++k) trial_ms[4 + k] = ms_split[k];
+    }
     return VTX_OK;
 }
 
@@ -1504,8 +1537,11 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
     if (o->theta != VTX_THETA_LAMBDA && o->theta != VTX_THETA_P0)
         return set_error(VTX_E_ARG, "unknown theta selector");
     if (block_threads != 0 && block_threads != 256 && block_threads != 512 &&
-        block_threads != 1024)
-        return set_error(VTX_E_ARG, "block_threads must be 0, 256, 512 or 1024");
+        block_threads != 1024 && block_threads != -1 && block_threads != -2 &&
+        block_threads != -4 && block_threads != -8)
+        return set_error(VTX_E_ARG, "block_threads must be 0, 256, 512, 1024 or -1, -2, -4, -8");
+    if (block_threads < 0 && o->method == VTX_GRAD_ADJOINT_MINRES)
+        return set_error(VTX_E_ARG, "the multi-workgroup schedule takes CG or EP");
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)b->ts.size();
     std::vector<GradItem> items(n);
@@ -1532,13 +1568,44 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         if (e != hipSuccess) return hip_fail(e);
         GradOpts go{o->cg_tol, o->cg_max_iter, o->theta, o->method == VTX_GRAD_ADJOINT_MINRES};
         const GradItem *gi = (const GradItem *)b->gitems;
-        int rc;
-        if (mode == VTX_F32)
-            rc = launch_batch_cg<float, float>(b, gi, n, go, block_threads, s);
+        int rc = VTX_OK;
+        int K = 0, n_groups = 0, lds = 0;
+        if (block_threads < 0 && (mode != VTX_F64 || go.minres))
+            return set_error(VTX_E_ARG, "the multi-workgroup adjoint runs FP64 CG only");
+        if (block_threads < 0 && (rc = plan_mb(b, block_threads, &K, &n_groups, &lds)))
+            return rc;
+        if (K > 0) {
+            // a tissue whose result is never written keeps status -1 (an error)
+            e = hipMemsetAsync(b->gres_d, 0xff, sizeof(vtx_grad_result) * n, s);
+            if (e == hipSuccess)
+                e = mb_launch(gi, b->order_d, n, go, K, n_groups, lds, b->gres_d, b->mb_groups,
+                              s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(res, b->gres_d, sizeof(vtx_grad_result) * n,
+                                   hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e);
+            // tissues a part could not hold go to the one-workgroup kernel
+            std::vector<int32_t> rest;
+            for (int i = 0; i < n; ++i)
+                if (res[i].status == mb_no_fit_status()) rest.push_back(i);
+            if (rest.empty()) {
+                for (int i = 0; i < n; ++i)
+                    if (res[i].status < 0 || res[i].status > VTX_CG_MAXITER)
+                        return set_error(VTX_E_HIP, "multi-workgroup adjoint: a wait between "
+                                                    "the workgroups of a tissue timed out");
+                return VTX_OK;
+            }
+            e = hipMemcpyAsync(b->order2_d, rest.data(), sizeof(int32_t) * rest.size(),
+                               hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(e);
+            rc = launch_batch_cg<double, double>(b, gi, b->order2_d, (int)rest.size(), go, 0, s);
+        } else if (mode == VTX_F32)
+            rc = launch_batch_cg<float, float>(b, gi, b->order_d, n, go, block_threads, s);
         else if (mode == VTX_F64)
-            rc = launch_batch_cg<double, double>(b, gi, n, go, block_threads, s);
+            rc = launch_batch_cg<double, double>(b, gi, b->order_d, n, go, block_threads, s);
         else
-            rc = launch_batch_cg<double, float>(b, gi, n, go, block_threads, s);
+            rc = launch_batch_cg<double, float>(b, gi, b->order_d, n, go, block_threads, s);
         if (rc) return rc;
         e = hipMemcpyAsync(res, b->gres_d, sizeof(vtx_grad_result) * n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1564,14 +1631,17 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
         if (e != hipSuccess) return hip_fail(e);
     }
     std::vector<vtx_relax_result> rp(n), rm(n);
+    // block_threads < 0: the nudged relaxations split each tissue over
+    // -block_threads workgroups
+    const int split = block_threads < 0 ? -block_threads : 0;
+    const int bt = block_threads < 0 ? 0 : block_threads;
     // first-order EP: one relaxation nudged by beta; the other state stays X*
     rc = batch_relax_run(b, mode, Xp.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
-                         centred ? 0.5 * o->beta : o->beta, block_threads, rp.data(), s);
+                         centred ? 0.5 * o->beta : o->beta, bt, rp.data(), s, split);
     if (rc) return rc;
     if (centred) {
         rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target,
-                             X_target ? nullptr : dC_dX, -0.5 * o->beta, block_threads, rm.data(),
-                             s);
+                             X_target ? nullptr : dC_dX, -0.5 * o->beta, bt, rm.data(), s, split);
         if (rc) return rc;
     }
     for (int i = 0; i < n; ++i) items[i].X = Xp[i];

@@ -24,7 +24,7 @@ THETA_LAMBDA, THETA_P0 = 0, 1
 GRAD_ADJOINT, GRAD_EP_CENTRED, GRAD_EP_FORWARD, GRAD_ADJOINT_MINRES = 0, 1, 2, 3
 _METHODS = {"adjoint": GRAD_ADJOINT, "adjoint_minres": GRAD_ADJOINT_MINRES,
             "ep": GRAD_EP_CENTRED, "ep_centred": GRAD_EP_CENTRED, "ep_forward": GRAD_EP_FORWARD}
-SCHED_AUTO, SCHED_PERSISTENT, SCHED_GRID = -1, 0, 1
+SCHED_AUTO, SCHED_PERSISTENT, SCHED_GRID, SCHED_SPLIT = -1, 0, 1, 2
 
 _MODE_NAMES = {"f32": F32, "f64": F64, "mixed": MIXED}
 
@@ -405,8 +405,9 @@ class Batch:
         """schedule: SCHED_PERSISTENT (one workgroup of `block_threads` per
         tissue: 256, 512 or 1024, or 0 to let the library choose, which takes
         the LDS-resident kernel when every tissue fits it), SCHED_GRID (each
-        tissue in turn on the whole GPU) or SCHED_AUTO (timed trials pick
-        one)."""
+        tissue in turn on the whole GPU), SCHED_SPLIT (T1 off: each tissue
+        over `block_threads` = 1, 2, 4 or 8 cooperating workgroups, 0
+        chooses) or SCHED_AUTO (timed trials pick one)."""
         m = _mode(mode)
         xs, cps, keep = self._marshal(Xs, params_list, m)
         o = relax_opts(**opts)
@@ -417,12 +418,13 @@ class Batch:
 
     def autotune(self, Xs, params_list, mode="mixed", trial_iters=200, **opts):
         """(schedule, block_threads, projected trial times in ms for persistent
-        256/512/1024 and grid); Xs are not modified."""
+        256/512/1024, grid and split 2/4/8 (-1: not tried, T1 on)); Xs are
+        not modified."""
         m = _mode(mode)
         xs, cps, keep = self._marshal(Xs, params_list, m)
         o = relax_opts(**opts)
         sch, bt = C.c_int32(), C.c_int32()
-        ms = (C.c_double * 4)()
+        ms = (C.c_double * 7)()
         _check(lib().vtx_batch_autotune(self._h, m, xs, cps, C.byref(o), int(trial_iters),
                                         C.byref(sch), C.byref(bt), ms, _stream()))
         return sch.value, bt.value, list(ms)
@@ -434,7 +436,8 @@ class Batch:
         (one workgroup of `block_threads` per tissue: 256, 512 or 1024, or 0
         to let the library choose; for CG on tissues of up to 1024 cells it
         takes 512 threads, which keep each solve's topology and vectors in
-        LDS and registers)."""
+        LDS and registers; -K splits each tissue over K = 1, 2, 4 or 8
+        cooperating workgroups: FP64 CG, or the nudged relaxations of EP)."""
         m = _mode(mode)
         n = len(self.tissues)
         keep = []

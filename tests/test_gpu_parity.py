@@ -769,7 +769,7 @@ def test_batch_schedules_agree(vtx):
             print("autotune", sch, bt_best, ms)
             assert sch in (vtx.SCHED_PERSISTENT, vtx.SCHED_GRID)
             assert bt_best in ((256, 512, 1024) if sch == vtx.SCHED_PERSISTENT else (0,))
-            assert all(m > 0 for m in ms)
+            assert all(m > 0 for m in ms[:4]) and ms[4:] == [-1.0] * 3   # T1 on: no split
             assert all(torch.equal(a, b) for a, b in zip(X0, Xs))  # trials leave X alone
         res = B.relax(Xs, ps, mode="mixed", schedule=sched, block_threads=bt, **opts)
         runs.append((res, [X.cpu().numpy() for X in Xs], [T.topology() for T in Ts]))
@@ -781,6 +781,49 @@ def test_batch_schedules_agree(vtx):
             np.testing.assert_array_equal(h, h0)
             assert np.abs(x - x0).max() < 1e-9
             assert r["energy"] == pytest.approx(r0["energy"], rel=1e-7)
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed", "f32"])
+def test_batch_relax_split_schedule(vtx, errlog, mode):
+    """The split schedule (T1 off; each tissue over K cooperating
+    workgroups) reproduces the single-tissue relaxation bit for bit for
+    K = 1, 2, 4, 8 and the library's choice, on tissues of 64 to 2600 cells
+    (with K = 1 the tissues of more than 1024 vertices fall back to the
+    persistent kernel); the autotuner then also times it."""
+    rng = np.random.default_rng(47)
+    cases = [_batch_case(rng, n, P0) for n, P0 in
+             ((64, 3.65), (300, 3.70), (1000, 3.72), (2600, 3.68))]
+    opts = dict(eta=3e-3, tol=1e-6, max_iter=8000, t1_enable=False)
+    dt = vtx.pos_dtype(mode)
+    refs = []
+    for t, p in cases:
+        T = vtx.Tissue.from_tissue(t)
+        Xd = _dev(t.X, dt)
+        r = T.relax(Xd, vtx.Params.from_numpy(p, dtype=dt), mode=mode, **opts)
+        refs.append((r, Xd.cpu().numpy()))
+    Ps = [vtx.Params.from_numpy(p, dtype=dt) for _, p in cases]
+    for K in (1, 2, 4, 8, 0):
+        Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
+        Xs = [_dev(t.X, dt) for t, _ in cases]
+        res = vtx.Batch(Ts).relax(Xs, Ps, mode=mode, schedule=vtx.SCHED_SPLIT,
+                                  block_threads=K, **opts)
+        for (rs, Xref), r, X, (t, _) in zip(refs, res, Xs, cases):
+            assert (r["status"], r["iters"]) == (rs["status"], rs["iters"]), (K, t.n_cell, r, rs)
+            d = np.abs(X.cpu().numpy() - Xref).max()
+            errlog(f"split relaxation {mode}, K={K}, {t.n_cell} cells: positions against the "
+                   "single path (max abs)", d)
+            assert d == 0.0
+            assert r["energy"] == pytest.approx(
+                rs["energy"], rel={"f64": 1e-10, "mixed": 1e-7, "f32": 1e-6}[mode])
+    Ts = [vtx.Tissue.from_tissue(t) for t, _ in cases]
+    Xs = [_dev(t.X, dt) for t, _ in cases]
+    sch, bt, ms = vtx.Batch(Ts).autotune(Xs, Ps, mode=mode, trial_iters=100, **opts)
+    print("autotune without T1", sch, bt, ms)
+    assert all(m > 0 for m in ms)
+    assert sch != vtx.SCHED_SPLIT or bt in (2, 4, 8)
+    with pytest.raises(vtx.VtxError):
+        vtx.Batch(Ts).relax(Xs, Ps, mode=mode, schedule=vtx.SCHED_SPLIT, block_threads=4,
+                            eta=3e-3, tol=1e-6, max_iter=10, t1_enable=True, l_min=0.01)
 
 
 # --------------------------------------------------- batched hypergradients
@@ -899,18 +942,81 @@ def test_batch_adjoint_lds_and_global_paths(vtx, block_threads):
         assert inf["status"] == 0, inf
         assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-7 * np.abs(gsingle).max()
     if block_threads == 1024:
-        # the library's own choice (1024 here: one tissue has too many cells
-        # for the register-resident form) gives the same gradients
-        outs0, _ = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=0)
-        for a, b_ in zip(outs0, outs):
-            assert torch.equal(a, b_)
+        # the library's own choice gives the same gradients
+        outs0, infos0 = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=0)
+        for a, b_, inf in zip(outs0, outs, infos0):
+            assert inf["status"] == 0, inf
+            assert float((a - b_).abs().max()) < 1e-7 * float(b_.abs().max())
         with pytest.raises(vtx.VtxError) as err:
             vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=128)
         assert err.value.code == -1
 
 
+@pytest.mark.parametrize("parts", [-1, -2, -4, -8])
+@pytest.mark.parametrize("theta", ["lambda", "P0"])
+def test_batch_adjoint_multiblock(vtx, oracle, errlog, small_equilibria, theta, parts):
+    """Each tissue split over 1, 2, 4 or 8 workgroups (block_threads = -K):
+    the gradients and CG iteration counts equal the single-tissue solve's
+    and the oracle's to the solve's tolerance."""
+    Ts, Xs, Ps, bs, refs = [], [], [], [], []
+    for t, m, X, p, Xt in small_equilibria:
+        T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
+        _, b = oracle.v2v(m, X, Xt)
+        go, info_o = oracle.adjoint_grad(m, X, p, b, theta=theta, tol=1e-10)
+        gs, info_s = T.param_grad(_dev(X), vtx.Params.from_numpy(p), dC_dX=_dev(b), theta=theta,
+                                  cg_tol=1e-10)
+        Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); bs.append(_dev(b))
+        refs.append((go, info_o, gs.cpu().numpy(), info_s))
+    outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, theta=theta, cg_tol=1e-10,
+                                           block_threads=parts)
+    worst = 0.0
+    for (go, info_o, gs, info_s), gb, inf in zip(refs, outs, infos):
+        assert inf["status"] == 0, inf
+        assert abs(inf["cg_iters"] - info_o["iters"]) <= 2
+        gb = gb.cpu().numpy()
+        worst = max(worst, np.abs(gb - go).max() / np.abs(go).max())
+        assert np.abs(gb - gs).max() < 1e-8 * np.abs(gs).max()
+        assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
+    errlog(f"batched adjoint, each tissue over {-parts} workgroups, theta={theta} "
+           "(max |dg| / max |g|, worst tissue)", worst)
+
+
+def test_batch_adjoint_multiblock_sizes_and_fallback(vtx):
+    """Hexagonal-lattice tissues of 120, 1088 and 2600 cells in one batch,
+    split over 8 workgroups (the largest part owns 650 vertices) and over 1
+    (the 2600-cell tissue does not fit one workgroup's share and goes to the
+    one-workgroup kernel): both equal the single-tissue solves."""
+    rng = np.random.default_rng(62)
+    s = np.sqrt(2.0 / (3.0 * np.sqrt(3.0)))
+    Ts, Xs, Ps, bs, singles = [], [], [], [], []
+    for nx, ny in [(12, 10), (34, 32), (52, 50)]:
+        t = g.hex_lattice(nx, ny, s)
+        p = g.uniform_params(t, P0=3.7)
+        p.lam = np.full(t.n_edge, 0.1)
+        T = vtx.Tissue.from_tissue(t)
+        P = vtx.Params.from_numpy(p)
+        X = _dev(t.X)
+        b = T.v2v(X, X + _dev(rng.normal(0, 0.05, t.X.shape)))[1]
+        gs, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-10)
+        assert info["status"] == 0, info
+        Ts.append(T); Xs.append(X); Ps.append(P); bs.append(b); singles.append(gs.cpu().numpy())
+    for parts in (-8, -1):
+        outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10,
+                                               block_threads=parts)
+        for gsingle, gb, inf in zip(singles, outs, infos):
+            assert inf["status"] == 0, (parts, inf)
+            assert np.abs(gb.cpu().numpy() - gsingle).max() < 1e-7 * np.abs(gsingle).max()
+    with pytest.raises(vtx.VtxError):
+        vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=-4,
+                                 method="adjoint_minres")
+
+
+@pytest.mark.parametrize("block_threads", [0, -2, -4])
 @pytest.mark.parametrize("method", ["ep", "ep_forward"])
-def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method):
+def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method, block_threads):
+    """Batched EP (the library's choice of relaxation kernel, or the nudged
+    relaxations split over 2 or 4 workgroups per tissue) against the
+    single-tissue path."""
     beta = 0.04
     ep = dict(eta=3e-3, tol=1e-12, max_iter=400000)
     Ts, Xs, Ps, Xts, refs = [], [], [], [], []
@@ -921,7 +1027,8 @@ def test_batch_ep_matches_single(vtx, oracle, small_equilibria, method):
         Ts.append(T); Xs.append(_dev(X)); Ps.append(vtx.Params.from_numpy(p)); Xts.append(_dev(Xt))
         refs.append(gs.cpu().numpy())
     B = vtx.Batch(Ts)
-    outs, infos = B.param_grad(Xs, Ps, X_target=Xts, method=method, beta=beta, ep_relax=ep)
+    outs, infos = B.param_grad(Xs, Ps, X_target=Xts, method=method, beta=beta, ep_relax=ep,
+                               block_threads=block_threads)
     for gsingle, gb, inf in zip(refs, outs, infos):
         assert inf["status"] == 0
         assert inf["ep_plus"]["iters"] > 1
@@ -970,27 +1077,57 @@ def test_autograd_equilibrium_gradient(vtx, oracle, small_equilibria, method):
     assert err < (1e-7 if method == "adjoint" else 1e-3)
 
 
-def test_gradient_matches_library_finite_differences(vtx, small_equilibria):
+def test_gradient_matches_library_finite_differences(vtx, small_equilibria, errlog):
     """Central differences of the relaxed v2v cost, all on the GPU (FP64
-    relaxations from X* without T1), along 4 random directions."""
+    relaxations from X* without T1 to max |F| < 1e-12), along 8 random unit
+    directions at h = 1e-3 and h/2: the two differ by their h^2 truncation
+    (ratio 4), Richardson's (4 FD(h/2) - FD(h)) / 3 equals adjoint . d to
+    1e-6, and centred EP (beta = 1e-3, nudged relaxations to 1e-12) equals
+    it within its budget c beta^2 + tol / (beta |grad C|) (here 1e-4),
+    first-order EP within its O(beta) bias (1e-2)."""
     t, m, X, p, Xt = small_equilibria[1]
     T = vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly)
     Xd, Xtd = _dev(X), _dev(Xt)
-
-    def cost(lam):
-        Xr = Xd.clone()
-        r = T.relax(Xr, vtx.Params(P0=3.75, lam=_dev(lam)), mode="f64", eta=3e-3, tol=1e-12,
-                    max_iter=1000000)
-        assert r["status"] == 0
-        C, _ = T.v2v(Xr, Xtd)
-        return C.item()
-
-    _, b = T.v2v(Xd, Xtd)
-    gg, info = T.param_grad(Xd, vtx.Params.from_numpy(p), dC_dX=b, cg_tol=1e-12)
+    P = vtx.Params.from_numpy(p)
+    X0 = Xd.clone()
+    assert T.relax(X0, P, mode="f64", eta=3e-3, tol=1e-12, max_iter=2000000)["status"] == 0
+    _, b = T.v2v(X0, Xtd)
+    gg, info = T.param_grad(X0, P, dC_dX=b, cg_tol=1e-13)
+    ep = dict(eta=3e-3, tol=1e-12, max_iter=2000000)
+    ge, ie = T.param_grad(X0, P, X_target=Xtd, method="ep", beta=1e-3, ep_relax=ep)
+    gf, if_ = T.param_grad(X0, P, X_target=Xtd, method="ep_forward", beta=1e-3, ep_relax=ep)
+    assert info["status"] == 0 and ie["status"] == 0 and if_["status"] == 0
     rng = np.random.default_rng(8)
-    for _ in range(4):
+    dirs, Ts, Xs, Ps = [], [], [], []
+    for _ in range(8):
         d = rng.normal(size=t.n_edge)
         d /= np.linalg.norm(d)
-        h = 1e-3
-        fd = (cost(p.lam + h * d) - cost(p.lam - h * d)) / (2 * h)
-        assert gg.cpu().numpy() @ d == pytest.approx(fd, rel=2e-3, abs=1e-9)
+        dirs.append(d)
+        for h in (1e-3, 5e-4):
+            for sgn in (1.0, -1.0):
+                Ts.append(vtx.Tissue(m.he, t.n_vert, t.Lx, t.Ly))
+                Xs.append(X0.clone())
+                Ps.append(vtx.Params(P0=3.75, lam=_dev(p.lam + sgn * h * d)))
+    res = vtx.Batch(Ts).relax(Xs, Ps, mode="f64", eta=3e-3, tol=1e-12, max_iter=2000000)
+    assert all(r["status"] == 0 for r in res)
+    Cs = [Ti.v2v(Xi, Xtd)[0].item() for Ti, Xi in zip(Ts, Xs)]
+    worst = {"adjoint vs Richardson": 0.0, "adjoint vs FD(h/2)": 0.0, "centred EP": 0.0,
+             "first-order EP": 0.0}
+    for j, d in enumerate(dirs):
+        fd_h = (Cs[4 * j] - Cs[4 * j + 1]) / 2e-3
+        fd_h2 = (Cs[4 * j + 2] - Cs[4 * j + 3]) / 1e-3
+        rich = (4 * fd_h2 - fd_h) / 3
+        a = float(gg.cpu().numpy() @ d)
+        # the truncation error shrinks four-fold with h (or is below the
+        # relaxation noise)
+        assert abs(fd_h - a) > 3 * abs(fd_h2 - a) or abs(fd_h - a) < 1e-6 * abs(a)
+        for key, val, ref in (("adjoint vs Richardson", a, rich), ("adjoint vs FD(h/2)", a, fd_h2),
+                              ("centred EP", float(ge.cpu().numpy() @ d), a),
+                              ("first-order EP", float(gf.cpu().numpy() @ d), a)):
+            worst[key] = max(worst[key], abs(val - ref) / abs(ref))
+    for key, v in worst.items():
+        errlog(f"finite differences, 20-cell tissue, 8 directions: {key} (relative)", v)
+    assert worst["adjoint vs Richardson"] < 1e-6
+    assert worst["adjoint vs FD(h/2)"] < 1e-5
+    assert worst["centred EP"] < 1e-4
+    assert worst["first-order EP"] < 1e-2
