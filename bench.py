@@ -1,26 +1,33 @@
 #!/usr/bin/env python
 """Benchmark of the vertex-model hot path on one MI355X.
 
-Workload (the force-kernel throughput case): one periodic Voronoi tissue of
-10^6 cells (uniform-random seeds, box side 1000; 2e6 3-valent vertices, 3e6
-edges), FP32 positions, K_A = A0 = K_P = 1, P0 = 3.75, per-edge lambda ~
-U[0.05, 0.15], fixed topology.  One step is one energy + force evaluation
-(cell pass + vertex pass + deterministic FP64 energy/max-force reductions);
-steps are replayed from a captured graph, inputs resident in HBM.
+Headline workload (the force-kernel throughput case): one periodic Voronoi
+tissue of 10^6 cells (uniform-random seeds, box side 1000; 2e6 3-valent
+vertices, 3e6 edges), FP32 positions, K_A = A0 = K_P = 1, P0 = 3.75,
+per-edge lambda ~ U[0.05, 0.15], fixed topology.  One step is one energy +
+force evaluation (cell pass + vertex pass + deterministic FP64 energy and
+max-force reductions), replayed from captured graphs with the inputs
+resident in HBM; exactly --warmup untimed and --steps timed evaluations.
 
 Printed: one JSON line with the whole-job vertex-force evaluations per
-second, the roofline of the dominant kernel (the vertex pass, timed alone
-with HIP events on the stream it is launched on; also with cold caches,
-after a 512 MiB write evicts the Infinity Cache), the oracle timed on the
-host cores as a CPU baseline, and (unless --no-secondary) the batched
-relaxation and hypergradient measurements.
+second; the roofline of the dominant kernel (the vertex pass, timed alone
+with HIP events on the stream it is launched on) against its algorithmic
+floor of 34 bytes per vertex (positions in, forces out, one 3-neighbour
+list, each edge tension once), warm (working set served partly from the
+256 MB Infinity Cache) and cold (after a 512 MiB write); the oracle timed on
+the host cores (one thread and all cores of the box's share); and, unless
+--no-secondary, the other workloads: the 100-cell and 10^4-cell single
+relaxations, the 512-tissue batched relaxation and the 64-tissue batched
+hypergradients.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -28,39 +35,231 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "vertex-force evals/s; param-gradients/s (batched adjoint vs plain) at 1e-6 tol"
+FLOOR_B_PER_VERTEX = 34   # positions in 8 + forces out 8 + 3-neighbour list 12 + lambda 6
+COUNTERS = os.path.join(ROOT, "profiles", "vertex_pass_1m_cells_counters.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(n_vert, n_cell, n_edge, n_he):
-    """Bytes each pass must move at least once (FP32 layout, ideal reuse)."""
+def design_bytes(n_vert, n_cell, n_edge, n_he):
+    """Bytes each pass of the current layout must move at least once (FP32)."""
     vertex = (n_vert * 8          # own position
               + n_vert * 36       # star: 3 neighbour ids, 3 cell ids, 3 edge ids
               + n_cell * 8        # (cA, cP) of every cell
               + n_edge * 4        # lambda of every edge
               + n_vert * 8)       # forces written
     cell = ((n_cell + 1) * 4      # row offsets
+            + n_cell * 4          # side counts
             + n_he * 4            # corner ids
             + n_vert * 8          # positions
             + n_cell * 8)         # (cA, cP) written
     return vertex, cell
 
 
-def read_traffic(path):
-    """HBM bytes per launch of the vertex pass from a committed counter
-    summary (FETCH_SIZE and WRITE_SIZE in KiB, scaled by the copy-kernel
-    calibration), or None."""
+def kernel_source_sha():
+    """Hash of the HIP sources, to tell whether committed counters still
+    describe the kernels that run."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2604_06896_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(path, sha):
+    """HBM bytes per vertex-pass launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
+    None if the summary is missing or was taken on other kernel sources."""
+    vals = {}
     try:
         with open(path) as f:
             for line in f:
-                if line.startswith("vertex_pass_bytes_per_launch:"):
-                    return float(line.split(":")[1])
+                if ":" in line and not line.startswith(("#", "|", " ")):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+    except OSError:
+        return None, "no counter summary"
+    if vals.get("kernel_source_sha") != sha:
+        return None, "counters taken on other kernel sources"
+    try:
+        return float(vals["vertex_pass_bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE"
+    except (KeyError, ValueError):
+        return None, "no vertex-pass figure in the counter summary"
+
+
+# --------------------------------------------------------------- CPU baseline
+# The oracle (plain FP64 C, one thread per process) on the box's host cores.
+# Each worker is a fresh process that loads the inputs from .npy files.
+
+def _worker(job):
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import oracle as O
+    kind, d, arg = job
+
+    def load(name):
+        return np.load(os.path.join(d, name + ".npy"))
+
+    def params(prefix):
+        from types import SimpleNamespace
+        return SimpleNamespace(KA=load(prefix + "KA"), A0=load(prefix + "A0"), KP=load(prefix + "KP"),
+                               P0=load(prefix + "P0"), lam=load(prefix + "lam"))
+
+    if kind == "eval":          # energy + forces, repeated for `arg` seconds
+        m = O.Mesh(load("c3_he"), int(load("c3_nv")), float(load("c3_L")), float(load("c3_L")))
+        X, p = load("c3_X"), params("c3_")
+        n, t0 = 0, time.perf_counter()
+        while True:
+            O.energy_forces(m, X, p)
+            n += 1
+            if time.perf_counter() - t0 > arg:
+                break
+        return n, time.perf_counter() - t0
+    if kind == "relax":         # a fixed number of relaxation steps
+        pre, opts = arg
+        m = O.Mesh(load(pre + "he"), int(load(pre + "nv")), float(load(pre + "L")),
+                   float(load(pre + "L")))
+        X = load(pre + "X").copy()
+        t0 = time.perf_counter()
+        r = O.relax(m, X, params(pre), patience=1, **opts)
+        return r, time.perf_counter() - t0
+    if kind == "adjoint":       # one adjoint hypergradient (CG to 1e-8)
+        m = O.Mesh(load("c5_he"), int(load("c5_nv")), float(load("c5_L")), float(load("c5_L")))
+        X, p, b = load("c5_X"), params("c5_"), load("c5_b")
+        t0 = time.perf_counter()
+        _, info = O.adjoint_grad(m, X, p, b, tol=1e-8)
+        return info, time.perf_counter() - t0
+    raise ValueError(kind)
+
+
+def _host():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
     except OSError:
         pass
-    return None
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model}
 
+
+def cpu_baseline(t, X32, lam32, args, secondary_inputs):
+    """The oracle, untuned, on the machine's host cores: one thread and one
+    process per core of the box's share (at most 16), each process running
+    the plain single-threaded oracle on its own copy of the inputs."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from paper_2604_06896_amd import tissue_gen as g
+    host = _host()
+    P = max(1, min(16, host["affinity_cpus"] or 1))
+    d = tempfile.mkdtemp(prefix="vtx_bench_", dir="/tmp")
+
+    def save(name, a):
+        np.save(os.path.join(d, name + ".npy"), np.asarray(a))
+
+    def save_params(pre, p, nc, ne):
+        for k in ("KA", "A0", "KP", "P0"):
+            save(pre + k, np.broadcast_to(getattr(p, k), (nc,)).astype(np.float64))
+        save(pre + "lam", np.broadcast_to(p.lam, (ne,)).astype(np.float64))
+
+    # config 3: the headline tissue, FP64 upcast of the FP32 inputs
+    save("c3_he", t.he)
+    save("c3_nv", t.n_vert)
+    save("c3_L", t.Lx)
+    save("c3_X", X32.astype(np.float64))
+    p3 = g.uniform_params(t, P0=3.75)
+    p3.lam = lam32.astype(np.float64)
+    save_params("c3_", p3, t.n_cell, t.n_edge)
+    for pre, (tt, pp, _) in secondary_inputs.items():
+        save(pre + "he", tt.he)
+        save(pre + "nv", tt.n_vert)
+        save(pre + "L", tt.Lx)
+        save(pre + "X", tt.X)
+        save_params(pre, pp, tt.n_cell, tt.n_edge)
+    ctx = mp.get_context("spawn")
+    out = {"kind": "oracle", "host": host}
+    with ctx.Pool(P) as pool:
+        s = args.cpu_seconds
+        n1, dt1 = pool.apply(_worker, (("eval", d, s),))
+        one = t.n_vert * n1 / dt1
+        res = pool.map(_worker, [("eval", d, s)] * P)
+        allc = sum(t.n_vert * n / dt for n, dt in res)
+        log(f"oracle, 1e6 cells: {one:.3e} vertex-force evals/s on one thread, {allc:.3e} on {P}")
+        out.update({"value": allc, "unit": "vertex-force evals/s", "cores": P,
+                    "single_thread": one,
+                    "sample": f"FP64 energy+force evaluations of the same 1e6-cell tissue for "
+                              f"{s:.0f} s: {n1} on one thread, {sum(n for n, _ in res)} in "
+                              f"{P} processes (one per core)"})
+        if "c1_" in secondary_inputs:
+            (r, dt), (r2, dt2) = pool.map(_worker, [
+                ("relax", d, ("c1_", dict(eta=1e-2, tol=1e-6, max_iter=200000, t1_enable=True,
+                                           l_min=0.01))),
+                ("relax", d, ("c1_", dict(eta=1e-2, tol=1e-6, max_iter=20000,
+                                           t1_enable=False)))])
+            out["config1"] = {"with_t1": {"iters": r["iters"], "n_t1": r["n_t1"],
+                                          "status": r["status"], "s": dt},
+                              "without_t1_20000_steps": {"status": r2["status"],
+                                                         "max_f": r2["max_f"], "s": dt2}}
+            log(f"oracle, 100 cells: relaxation with T1 {r['iters']} steps in {dt:.2f}s")
+        if "c2_" in secondary_inputs:
+            n2 = secondary_inputs["c2_"][2]
+            r, dt = pool.apply(_worker, (("relax", d, ("c2_", dict(
+                eta=3e-3, tol=0.0, max_iter=n2, t1_enable=True, l_min=0.01))),))
+            out["config2"] = {"steps": n2, "s": dt, "ms_per_step": dt / n2 * 1e3}
+            log(f"oracle, 1e4 cells: {n2} relaxation steps with T1 in {dt:.2f}s")
+        c4 = sorted(k for k in secondary_inputs if k.startswith("c4_"))
+        if c4:
+            n4 = secondary_inputs[c4[0]][2]
+            res = pool.map(_worker, [("relax", d, (k, dict(eta=3e-3, tol=0.0, max_iter=n4,
+                                                           t1_enable=True, l_min=0.01)))
+                                     for k in c4])
+            vi = [secondary_inputs[k][0].n_vert * n4 / dt for k, (_, dt) in zip(c4, res)]
+            out["config4"] = {"tissues_sampled": len(c4), "steps_each": n4,
+                              "cells": [secondary_inputs[k][0].n_cell for k in c4],
+                              "vertex_iters_per_s_single_thread_median": float(np.median(vi)),
+                              "vertex_iters_per_s_all_cores": float(sum(vi)), "cores": len(c4)}
+            log(f"oracle, 512-tissue workload sample: {sum(vi):.3e} vertex-iterations/s on "
+                f"{len(c4)} cores")
+        if args.c5_fixture:
+            import sys as _s
+            _s.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+            import make_inverse_equilibrium as mk
+            t5, X5, p5 = mk.load()
+            rng = np.random.default_rng(7)
+            Xt5 = X5 + rng.normal(0, 0.05, X5.shape)
+            save("c5_he", t5.he)
+            save("c5_nv", t5.n_vert)
+            save("c5_L", t5.Lx)
+            save("c5_X", X5)
+            save("c5_b", (X5 - Xt5) / t5.n_vert)
+            save_params("c5_", p5, t5.n_cell, t5.n_edge)
+            res = pool.map(_worker, [("adjoint", d, None)] * P)
+            per = [dt for _, dt in res]
+            out["config5"] = {"adjoint_s_single_thread_median": float(np.median(per)),
+                              "cg_iters": int(res[0][0]["iters"]),
+                              "grads_per_s_all_cores": float(sum(1.0 / x for x in per)),
+                              "cores": P,
+                              "sample": "oracle adjoint (CG to 1e-8, FP64) of the first "
+                                        "1000-cell inverse-workload tissue at its oracle "
+                                        "equilibrium, v2v cost to a perturbed target, one "
+                                        "gradient per process"}
+            log(f"oracle adjoint, 1000 cells: {np.median(per):.2f} s per gradient on one thread")
+    for f in os.listdir(d):
+        os.remove(os.path.join(d, f))
+    os.rmdir(d)
+    return out
+
+
+# ---------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -69,25 +268,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--graph-evals", type=int, default=50, help="evaluations per captured graph")
     ap.add_argument("--kernel-reps", type=int, default=500)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-cell", type=int, default=1000000)
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the batched relaxation and hypergradient measurements")
+                    help="skip the other workloads (single relaxations, batched relaxation, "
+                         "hypergradients)")
     ap.add_argument("--batch-tissues", type=int, default=512)
     ap.add_argument("--batch-max-iter", type=int, default=200000)
     ap.add_argument("--grad-tissues", type=int, default=64)
-    ap.add_argument("--plain-sample", type=int, default=2)
+    ap.add_argument("--plain-sample", type=int, default=16)
     ap.add_argument("--cold-reps", type=int, default=50,
                     help="evaluations timed one by one after a 512 MiB cache flush")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (known bytes) to calibrate "
                          "hardware traffic counters")
     args = ap.parse_args()
+    args.c5_fixture = os.path.exists(os.path.join(ROOT, "tests", "golden",
+                                                  "inverse_tissue0_equilibrium.txt"))
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library "
               "runs on a single MI355X and has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -120,14 +325,19 @@ def main():
         log("copy calibration: 10 x 268435456-byte device copies")
         del src, dst
 
-    G = max(1, min(args.graph_evals, args.steps))
-    steps = (args.steps // G) * G
-    warm = max(G, (args.warmup // G) * G)
-
     def one_eval():
         T.energy_forces_into(X, cp, E, F, mf, mode="f32")
 
-    # eager warm-up, then capture G evaluations in one graph
+    def capture(fn, n):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            for _ in range(n):
+                fn()
+        return gr
+
+    # eager warm-up of the library (not counted), then graphs of G
+    # evaluations and of the remainders, so that exactly --warmup and
+    # --steps evaluations run
     for _ in range(3):
         one_eval()
     torch.cuda.synchronize()
@@ -136,14 +346,23 @@ def main():
     with torch.cuda.stream(s):
         one_eval()
     torch.cuda.current_stream().wait_stream(s)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for _ in range(G):
-            one_eval()
-    for _ in range(warm // G):
-        graph.replay()
+    G = max(1, args.graph_evals)
+    graphs = {G: capture(one_eval, G)}
+
+    def run_evals(n):
+        for _ in range(n // G):
+            graphs[G].replay()
+        r = n % G
+        if r:
+            if r not in graphs:
+                graphs[r] = capture(one_eval, r)
+            graphs[r].replay()
+
+    run_evals(args.steps % G or G)       # capture the remainder graph before timing
     torch.cuda.synchronize()
-    # check the replayed evaluation against an eager one
+    run_evals(args.warmup)
+    torch.cuda.synchronize()
+    # check a replayed evaluation against an eager one
     E_g, F_g = E.clone(), F.clone()
     one_eval()
     torch.cuda.synchronize()
@@ -153,14 +372,14 @@ def main():
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record()
-    for _ in range(steps // G):
-        graph.replay()
+    run_evals(args.steps)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
+    steps = args.steps
     value = t.n_vert * steps / (ms / 1e3)
-    log(f"{steps} evaluations in {ms:.2f} ms (wall {wall * 1e3:.2f} ms): "
+    log(f"{steps} evaluations in {ms:.3f} ms (wall {wall * 1e3:.2f} ms): "
         f"{ms / steps * 1e3:.2f} us/eval, E = {E.item():.6f}, max|F| = {mf.item():.4f}")
 
     # ---- dominant kernel alone: vertex pass (and cell pass), HIP events on
@@ -169,10 +388,7 @@ def main():
     R = max(G, (args.kernel_reps // G) * G)
 
     def timed_graph(fn):
-        gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr):
-            for _ in range(G):
-                fn()
+        gr = capture(fn, G)
         gr.replay()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -187,22 +403,19 @@ def main():
     v_ms = timed_graph(lambda: T.vertex_forces_into(X, cp, coeffs, F2, mode="f32"))
     c_ms = timed_graph(lambda: V.lib().vtx_cell_coeffs(T.handle, V.F32, V._ptr(X), V.C.byref(cp),
                                                        V._ptr(coeffs), V._stream()))
-    vb, cb = algorithmic_bytes(t.n_vert, t.n_cell, t.n_edge, t.n_he)
-    v_gbs = vb / (v_ms / 1e3) / 1e9
-    c_gbs = cb / (c_ms / 1e3) / 1e9
-    log(f"vertex pass {v_ms * 1e3:.2f} us ({v_gbs:.0f} GB/s algorithmic), "
-        f"cell pass {c_ms * 1e3:.2f} us ({c_gbs:.0f} GB/s)")
-    traffic = read_traffic(os.path.join(ROOT, "profiles", "vertex_pass_1m_cells_counters.txt"))
+    vb, cb = design_bytes(t.n_vert, t.n_cell, t.n_edge, t.n_he)
+    floor = FLOOR_B_PER_VERTEX * t.n_vert
+    log(f"vertex pass {v_ms * 1e3:.2f} us ({floor / v_ms / 1e6:.0f} GB/s of the 34 B/vertex "
+        f"floor, {vb / v_ms / 1e6:.0f} GB/s of its design bytes), cell pass {c_ms * 1e3:.2f} us "
+        f"({cb / c_ms / 1e6:.0f} GB/s)")
+    sha = kernel_source_sha()
+    traffic, traffic_src = read_traffic(COUNTERS, sha)
 
     # ---- cold caches: 512 MiB written between evaluations (not timed), so
     # that nothing of the ~180 MB an evaluation touches is left in the
     # 256 MB Infinity Cache or the L2s
-    g1 = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g1):
-        one_eval()
-    gv1 = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(gv1):
-        T.vertex_forces_into(X, cp, coeffs, F2, mode="f32")
+    g1 = capture(one_eval, 1)
+    gv1 = capture(lambda: T.vertex_forces_into(X, cp, coeffs, F2, mode="f32"), 1)
     flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
 
     def cold(gr, n):
@@ -219,45 +432,65 @@ def main():
     cold_eval_ms = cold(g1, args.cold_reps)
     cold_v_ms = cold(gv1, args.cold_reps)
     del flush, g1, gv1
-    log(f"cold caches: evaluation {cold_eval_ms * 1e3:.2f} us, vertex pass {cold_v_ms * 1e3:.2f} us "
-        f"({vb / (cold_v_ms / 1e3) / 1e9:.0f} GB/s)")
+    log(f"cold caches: evaluation {cold_eval_ms * 1e3:.2f} us, vertex pass {cold_v_ms * 1e3:.2f} "
+        f"us ({floor / cold_v_ms / 1e6:.0f} GB/s of the floor)")
 
-    # ---- CPU baseline: the oracle on the same input (FP64 upcast of X)
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle as O
-        O.build(force=False)
-        m = O.Mesh.from_tissue(t)
-        Xh = X.double().cpu().numpy()
-        pin = g.uniform_params(t, P0=3.75)
-        pin.lam = lam.double().cpu().numpy()
-        n = 0
-        c0 = time.perf_counter()
-        while True:
-            O.energy_forces(m, Xh, pin)
-            n += 1
-            if time.perf_counter() - c0 > args.cpu_seconds:
-                break
-        dt = time.perf_counter() - c0
-        cpu = {"value": t.n_vert * n / dt, "unit": "vertex-force evals/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{n} full FP64 energy+force evaluations of the same 1e6-cell tissue "
-                         f"({dt:.1f} s, one host thread)"}
-        log(f"oracle: {n} evaluations in {dt:.1f}s")
+    roofline = {
+        "bound": "hbm", "kernel": "k_vertex (vertex pass)",
+        "achieved": floor / v_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": floor / v_ms / 1e6 / HBM_PEAK_GBS, "traffic": traffic,
+        "bytes_per_launch": floor,
+        "bytes_basis": "algorithmic floor, 34 B per vertex: positions in 8, forces out 8, one "
+                       "3-neighbour list 12, each edge tension once 6",
+        "us_per_launch": v_ms * 1e3,
+        "timing": "warm: launches back to back, the ~180 MB working set partly served from the "
+                  "256 MB Infinity Cache",
+        "traffic_source": traffic_src,
+        "traffic_over_floor": traffic / floor if traffic else None,
+        "design": {"bytes_per_launch": vb, "achieved": vb / v_ms / 1e6,
+                   "frac": vb / v_ms / 1e6 / HBM_PEAK_GBS,
+                   "basis": "the current layout's bytes, each array once: 62 B per vertex"},
+        "cold_caches": {"vertex_pass_us": cold_v_ms * 1e3,
+                        "achieved": floor / cold_v_ms / 1e6,
+                        "frac": floor / cold_v_ms / 1e6 / HBM_PEAK_GBS,
+                        "design_frac": vb / cold_v_ms / 1e6 / HBM_PEAK_GBS,
+                        "evaluation_us": cold_eval_ms * 1e3},
+        "cell_pass": {"us_per_launch": c_ms * 1e3, "design_bytes_per_launch": cb,
+                      "achieved": cb / c_ms / 1e6, "frac": cb / c_ms / 1e6 / HBM_PEAK_GBS},
+        "kernel_source_sha": sha,
+    }
+    del F2, coeffs
+    torch.cuda.empty_cache()
 
+    # ---- secondary workloads (GPU), then the oracle on the host cores
     secondary = None
+    sec_inputs = {}
     if not args.no_secondary:
         from paper_2604_06896_amd import suite
-        del F2, coeffs
-        torch.cuda.empty_cache()
         secondary = {}
         w0 = time.perf_counter()
+        secondary["single_100_cells"] = suite.single_100(log=log)
+        c2 = suite.single_10k(log=log)
+        secondary["single_10k_cells"] = c2
         secondary["batched_relax"] = suite.batched_relax(
             n_tissue=args.batch_tissues, max_iter=args.batch_max_iter,
             plain_sample=args.plain_sample, block_threads=1024, log=log)
         secondary["param_gradients"] = suite.param_gradients(
-            n_tissue=args.grad_tissues, plain_sample=args.plain_sample, log=log)
+            n_tissue=args.grad_tissues, plain_sample=min(args.plain_sample, 8), log=log)
         log(f"secondary measurements took {time.perf_counter() - w0:.1f}s")
+        t1w, p1w = g.workload_single_100()
+        sec_inputs["c1_"] = (t1w, p1w, None)
+        t2w, p2w = g.workload_single_10k()
+        sec_inputs["c2_"] = (t2w, p2w, 50)
+        for k, (tk, pk) in enumerate(suite.batch_sample(16)):
+            sec_inputs[f"c4_{k:02d}_"] = (tk, pk, 500)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(t, X.cpu().numpy(), lam.cpu().numpy(), args, sec_inputs)
+        if secondary and "config2" in cpu:
+            c2 = secondary["single_10k_cells"]
+            cpu["config2"]["extrapolated_s_to_gpu_step_count"] = \
+                cpu["config2"]["ms_per_step"] * c2["iters"] / 1e3
 
     out = {
         "metric": METRIC,
@@ -265,7 +498,7 @@ def main():
         "unit": "vertex-force evals/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": warm,
+        "warmup": args.warmup,
         "ms_per_step": ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -277,15 +510,7 @@ def main():
                                "evaluation per step",
                    "n_cell": t.n_cell, "n_vert": t.n_vert, "n_edge": t.n_edge,
                    "graph_evals": G},
-        "roofline": {"bound": "hbm", "kernel": "k_vertex (vertex pass)",
-                     "achieved": v_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": v_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": vb, "us_per_launch": v_ms * 1e3,
-                     "cell_pass": {"achieved": c_gbs, "bytes_per_launch": cb,
-                                   "us_per_launch": c_ms * 1e3},
-                     "cold_caches": {"vertex_pass_us": cold_v_ms * 1e3,
-                                     "vertex_pass_achieved": vb / (cold_v_ms / 1e3) / 1e9,
-                                     "evaluation_us": cold_eval_ms * 1e3}},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "secondary": secondary,
     }
