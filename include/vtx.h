@@ -182,21 +182,27 @@ int vtx_tissue_get_topology(vtx_tissue t, int32_t *he_out);
  * creation). */
 int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he);
 
-/* Energy and forces at X (Methods, "Vertex model formulation").
+/* Energy and forces at X (Methods, "Vertex model formulation"), in one
+ * fused launch per tile of 256 vertices (plus a one-block finish for the
+ * scalars of large tissues).  F equals vtx_cell_coeffs followed by
+ * vtx_vertex_forces bit for bit; E equals the sum of the cell and edge
+ * energies up to the order of summation (fixed: deterministic).
  * E_dev: device double scalar or NULL; F: device [n_vert][2] or NULL;
  * maxf_dev: device double scalar (max |F| component) or NULL.
- * Asynchronous; graph-capturable. */
+ * Asynchronous; graph-capturable (a graph stays valid across topology
+ * changes: the tile tables are rebuilt in place, in stream order, by every
+ * call that changes the topology). */
 int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
                       double *E_dev, void *F, double *maxf_dev, void *stream);
 
 /* vtx_energy_forces for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc): the same kernels and results, with their scratch (per-cell
- * coefficients, per-block partial sums, control blocks) in a fixed device
- * array of the library (about 2.1 MiB, held on every GPU the library runs
- * on until the process ends) instead of the tissue's workspace.  Allocates
- * nothing and issues no memset (a small kernel clears the control blocks).
- * Limits: at most 131072 cells and 262144 vertices, else VTX_E_CAPACITY.
+ * hipMalloc): the same kernels and results, with their scratch (per-tile
+ * partial sums, control blocks) in a fixed device array of the library
+ * (about 17 KiB, held on every GPU the library runs on until the process
+ * ends) instead of the tissue's workspace.  Allocates nothing and issues no
+ * memset (a small kernel clears the control blocks).  Limit: at most 262144
+ * vertices (131072 cells), else VTX_E_CAPACITY.
  * All calls on one GPU share that array, so calls that overlap on one GPU
  * (different streams, threads or tissues) race; serialise them.  Arguments,
  * outputs and errors as vtx_energy_forces.  Asynchronous. */

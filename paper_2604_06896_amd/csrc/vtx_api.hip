@@ -14,23 +14,23 @@
 
 #include "vtx_launch.h"
 
+namespace vtx {
+int tissue_topology_changed(vtx_tissue t, hipStream_t s);
+}
+
 using namespace vtx;
 
 // ------------------------------------------------- allocation-free scratch
-// Fixed device scratch of vtx_energy_forces_noalloc: the per-cell
-// coefficients, the per-block partial sums and two loop control blocks of
-// one evaluation, for tissues of up to kNoAllocCells cells and
-// kNoAllocVerts vertices.  Every GPU the library runs on holds one copy
-// until the process ends.  In host code `scratch` names a host-side stand-in;
-// its device address comes from hipGetSymbolAddress (noalloc_scratch).
+// Fixed device scratch of vtx_energy_forces_noalloc: the per-tile partial
+// sums and two loop control blocks of one fused evaluation, for tissues of
+// up to kNoAllocVerts vertices (a 3-valent periodic tissue has half as many
+// cells).  Every GPU the library runs on holds one copy until the process
+// ends.  In host code `scratch` names a host-side stand-in; its device
+// address comes from hipGetSymbolAddress (noalloc_scratch).
 namespace {
-constexpr int64_t kNoAllocCells = 1 << 17;
 constexpr int64_t kNoAllocVerts = 1 << 18;
-constexpr size_t kNoAllocCapBytes = 16 * (size_t)kNoAllocCells;
-constexpr size_t kNoAllocPartBytes = 8 * (size_t)((kNoAllocCells + kBlock - 1) / kBlock);
-constexpr size_t kNoAllocMpartBytes = 16 * (size_t)((kNoAllocVerts + kBlock - 1) / kBlock);
-constexpr size_t kNoAllocCtlOffset =
-    (kNoAllocCapBytes + kNoAllocPartBytes + kNoAllocMpartBytes + 255) & ~(size_t)255;
+constexpr size_t kNoAllocMpartBytes = 16 * (size_t)((kNoAllocVerts + kTileV - 1) / kTileV);
+constexpr size_t kNoAllocCtlOffset = (kNoAllocMpartBytes + 255) & ~(size_t)255;
 constexpr size_t kNoAllocBytes = kNoAllocCtlOffset + ((2 * sizeof(LoopCtl) + 255) & ~(size_t)255);
 }  // namespace
 
@@ -47,6 +47,7 @@ __global__ void k_clear_ctl(LoopCtl *ctl) {
 struct vtx_tissue_s {
     DevTissue d;
     Workspace w;
+    TileTables tiles;    // fused evaluation; rebuilt in stream order after topology changes
     int64_t n_vert, n_cell, n_edge, n_he;
     double *ep_buf;      // two position buffers for EP (double-sized)
     int64_t t1_cap;
@@ -234,7 +235,9 @@ void free_tissue(vtx_tissue t) {
                     d.cell_he, d.star, d.star_he, t->w.xbuf,
                     t->w.cap, t->w.cell_aux, t->w.partials, t->w.partials2, t->w.mpart,
                     t->w.t1_list,
-                    t->w.ctl, t->w.cg, t->w.scal, t->ep_buf};
+                    t->w.ctl, t->w.cg, t->w.scal, t->ep_buf,
+                    t->tiles.cells, t->tiles.info, t->tiles.halo, t->tiles.cstart,
+                    t->tiles.corners, t->tiles.fstar, t->tiles.fe};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (t->w.ctl_host) (void)hipHostFree(t->w.ctl_host);
@@ -334,6 +337,10 @@ int relax_impl(vtx_tissue t, int mode, void *X, const vtx_params *p, const vtx_r
         const int cur = k & 1;
         launch_relax_iter(t->d, t->w, mode, bufs[cur], bufs[cur ^ 1], cur, raw(p), ra, cs);
     });
+    if (ra.t1_enable) {
+        const int rt = vtx::tissue_topology_changed(t, s);
+        if (!rc) rc = rt;
+    }
     if (rc) return rc;
     const LoopCtl &h = t->w.ctl_host[0];
     if (h.result_buf == 1) HIPCHK(hipMemcpyAsync(X, t->w.xbuf, pos_bytes(t, mode),
@@ -371,6 +378,10 @@ int64_t tissue_size(vtx_tissue t) { return t->n_vert; }
 int64_t tissue_cells(vtx_tissue t) { return t->n_cell; }
 double *tissue_ep_buf(vtx_tissue t) { return t->ep_buf; }
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+int tissue_topology_changed(vtx_tissue t, hipStream_t s) {
+    launch_tile_build(t->d, t->tiles, s);
+    return check_launch("tile tables");
+}
 }  // namespace vtx
 
 extern "C" {
@@ -446,6 +457,14 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
     A((void **)&w.cg, 6 * 16 * (size_t)n_vert);  // CG: 4 vectors, MINRES: 6
     A((void **)&w.scal, 16 * sizeof(double));
     A((void **)&t->ep_buf, 2 * 16 * (size_t)n_vert);
+    const size_t n_tiles = (size_t)n_tiles_for(n_vert);
+    A((void **)&t->tiles.cells, 4 * (size_t)kTileCap * n_tiles);
+    A((void **)&t->tiles.info, 16 * n_tiles);
+    A((void **)&t->tiles.halo, 4 * (size_t)kHaloCap * n_tiles);
+    A((void **)&t->tiles.cstart, 2 * (size_t)kCstartPad * n_tiles);
+    A((void **)&t->tiles.corners, 2 * (size_t)kCornerCap * n_tiles);
+    A((void **)&t->tiles.fstar, 16 * (size_t)n_vert);
+    A((void **)&t->tiles.fe, 8 * (size_t)n_vert);
     if (e == hipSuccess) e = hipHostMalloc((void **)&w.ctl_host, 2 * sizeof(LoopCtl), 0);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) {
@@ -453,6 +472,11 @@ int vtx_tissue_create(const int32_t *he, int64_t n_he, int64_t n_vert, int64_t n
         w.ctl_host[0] = z;
         w.ctl_host[1] = z;
         e = hipMemcpy(w.ctl, w.ctl_host, 2 * sizeof(LoopCtl), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        launch_tile_build(d, t->tiles, nullptr);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
     }
     if (e != hipSuccess) {
         free_tissue(t);
@@ -503,13 +527,14 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he) {
         (rc = upload_into(d.nsides, S.nsides)) || (rc = upload_into(d.cell_he, S.cell_he)) ||
         (rc = upload_into(d.star, S.star)) || (rc = upload_into(d.star_he, S.star_he)))
         return rc;
-    return VTX_OK;
+    return vtx::tissue_topology_changed(t, nullptr);
 }
 
 int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
                       double *E_dev, void *F, double *maxf_dev, void *stream) {
     if (!t || !X || !p || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
-    launch_eval(t->d, t->w, mode, X, raw(p), E_dev, F, maxf_dev, (hipStream_t)stream);
+    launch_eval_fused(t->d, t->w, t->tiles, mode, X, raw(p), E_dev, F, maxf_dev,
+                      (hipStream_t)stream);
     return check_launch("vtx_energy_forces");
 }
 
@@ -546,23 +571,20 @@ extern "C" {
 int vtx_energy_forces_noalloc(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,
                               double *E_dev, void *F, double *maxf_dev, void *stream) {
     if (!t || !X || !p || !mode_ok(mode)) return fail(VTX_E_ARG, "bad argument");
-    if (t->n_cell > kNoAllocCells || t->n_vert > kNoAllocVerts)
+    if (t->n_vert > kNoAllocVerts)
         return fail(VTX_E_CAPACITY,
-                    "vtx_energy_forces_noalloc: %lld cells / %lld vertices exceed its fixed "
-                    "scratch (at most %lld cells and %lld vertices)",
-                    (long long)t->n_cell, (long long)t->n_vert, (long long)kNoAllocCells,
-                    (long long)kNoAllocVerts);
+                    "vtx_energy_forces_noalloc: %lld vertices exceed its fixed scratch (at most "
+                    "%lld vertices)",
+                    (long long)t->n_vert, (long long)kNoAllocVerts);
     int rc = VTX_OK;
     unsigned char *base = noalloc_scratch(&rc);
     if (!base) return rc;
     hipStream_t s = (hipStream_t)stream;
     Workspace w{};
-    w.cap = (double *)base;
-    w.partials = (double *)(base + kNoAllocCapBytes);
-    w.mpart = (double *)(base + kNoAllocCapBytes + kNoAllocPartBytes);
+    w.mpart = (double *)base;
     w.ctl = (LoopCtl *)(base + kNoAllocCtlOffset);
     hipLaunchKernelGGL(k_clear_ctl, dim3(1), dim3(64), 0, s, w.ctl);
-    launch_eval(t->d, w, mode, X, raw(p), E_dev, F, maxf_dev, s);
+    launch_eval_fused(t->d, w, t->tiles, mode, X, raw(p), E_dev, F, maxf_dev, s);
     return check_launch("vtx_energy_forces_noalloc");
 }
 
@@ -609,6 +631,7 @@ int vtx_t1(vtx_tissue t, int32_t mode, void *X, const vtx_params *p, double l_mi
     if (rc) return rc;
     launch_t1(t->d, t->w, mode, X, raw(p), l_min, l_new, s);
     if ((rc = check_launch("vtx_t1"))) return rc;
+    if ((rc = vtx::tissue_topology_changed(t, s))) return rc;
     if ((rc = read_ctl(t, 1, s))) return rc;
     const LoopCtl h = t->w.ctl_host[1];
     if (n_swap) *n_swap = h.n_t1;

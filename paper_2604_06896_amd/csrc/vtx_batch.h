@@ -16,6 +16,9 @@ int64_t tissue_size(vtx_tissue t);
 int64_t tissue_cells(vtx_tissue t);
 double *tissue_ep_buf(vtx_tissue t);
 int set_error(int code, const char *msg);
+// Rebuild the tissue's fused-evaluation tables after its topology changed
+// (on stream s, in order with the change).
+int tissue_topology_changed(vtx_tissue t, hipStream_t s);
 }  // namespace vtx
 
 namespace vtx {

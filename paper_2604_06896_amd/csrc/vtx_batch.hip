@@ -1295,6 +1295,11 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
             hipLaunchKernelGGL((k_batch_relax<double, float>), grid, block, 0, cs, it, b->order_d,
                                n, b->queue, bo, b->res_d);
     });
+    if (t1)
+        for (int i = 0; i < n; ++i) {
+            const int rt = tissue_topology_changed(b->ts[i], s);
+            if (!rc) rc = rt;
+        }
     if (rc) return rc;
     e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -43,7 +43,7 @@ __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__rest
         const M dx = rx - px, dy = ry - py;
         const M l2 = dx * dx + dy * dy;
         a += px * ry - py * rx;
-        per += sqrt(l2);
+        per += len_of(l2);
         if (det && l2 < lmin2 && vprev < v) {
             unsigned int s = atomicAdd(count, 1u);
             list[s] = row_base + k - 1;
@@ -60,7 +60,7 @@ __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__rest
         step(k, wk, ld2(X, id_of(wk)));
     }
     const M l2 = px * px + py * py;  // closing edge, corner n-1 -> corner 0
-    per += sqrt(l2);
+    per += len_of(l2);
     if (det && l2 < lmin2 && vprev < v0) {
         unsigned int s = atomicAdd(count, 1u);
         list[s] = row_base + n - 1;
@@ -145,9 +145,9 @@ __device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<Pos
         s.cA[k] = L.cc[k].x;
         s.cP[k] = L.cc[k].y;
         s.lam[k] = (M)L.lam[k];
-        const M l = sqrt(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k]);
         // a zero-length edge contributes its minimum-norm subgradient, 0
-        const M inv = l > (M)0 ? (M)1 / l : (M)0;
+        M l, inv;
+        len_inv(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k], l, inv);
         s.l[k] = l;
         s.inv[k] = inv;
         s.ux[k] = s.dx[k] * inv;
@@ -741,8 +741,8 @@ __device__ __forceinline__ void hvp_cell_row(const DevTissue &t, const PosT *__r
         const C gx = (C)0.5 * (rny - rpy), gy = (C)-0.5 * (rnx - rpx);
         dA += gx * vcx + gy * vcy;
         const C dx = rnx - rcx, dy = rny - rcy;
-        const C l = sqrt(dx * dx + dy * dy);
-        if (l > (C)0) dP += (dx * (vnx - vcx) + dy * (vny - vcy)) / l;
+        const C l2 = dx * dx + dy * dy;
+        if (l2 > (C)0) dP += over_len(dx * (vnx - vcx) + dy * (vny - vcy), l2);
         rpx = rcx;
         rpy = rcy;
         rcx = rnx;

@@ -111,6 +111,45 @@ struct LoopCtl {
     double mr_delta, mr_eps, mr_gamma, mr_tau, mr_beta_next;
 };
 
+// Tables of the fused evaluation (k_eval_fused), a tile-local copy of the
+// mesh.  Vertex tile b is the kTileV consecutive vertices from b * kTileV.
+// Its cells (every cell around one of its vertices, at most kTileCap) are
+// listed in slot b of `cells`, bit 31 set where tile b owns the cell (holds
+// its corner 0) so that each cell energy is counted once.  Its halo lists
+// the other vertices those cells and the tile's edges reach.  Local vertex
+// index j < kTileV is vertex b * kTileV + j, j >= kTileV is halo[j - kTileV].
+// Corner rows and star neighbours are stored as 16-bit local references:
+// local index in the low 12 bits, the periodic image (as in pack_id) in the
+// top 4.  Per vertex, `fstar` = {nb_0 | nb_1 << 16, nb_2, local cells (10
+// bits each), e_0} and `fe` = [2][n_vert] {e_1, e_2}.  A tile whose halo or
+// corner rows do not fit (info.z = 1) is evaluated from the global star and
+// rows instead.  Everything is derived from the star and the corner rows and
+// rebuilt whenever the topology changes.
+constexpr int kTileV = 256;
+constexpr int kTileCap = 3 * kTileV;        // cells per tile
+constexpr int kHaloCap = 768;               // halo vertices per tile
+constexpr int kCornerCap = 2048;            // corner references per tile
+constexpr int kCstartPad = kTileCap + 8;    // row starts per tile (uint16)
+struct TileTables {
+    int32_t *cells;     // [n_tiles][kTileCap]
+    int4 *info;         // [n_tiles] {cells, halo vertices, global fallback, corners}
+    int32_t *halo;      // [n_tiles][kHaloCap]
+    uint16_t *cstart;   // [n_tiles][kCstartPad] row start of each cell, then the end
+    uint16_t *corners;  // [n_tiles][kCornerCap]
+    int4 *fstar;        // [n_vert]
+    int32_t *fe;        // [2][n_vert]
+};
+__host__ __device__ inline int64_t n_tiles_for(int64_t n_vert) {
+    return (n_vert + kTileV - 1) / kTileV;
+}
+// 16-bit local reference <-> packed local id + image
+__host__ __device__ inline int32_t unpack_local(uint32_t r) {
+    return (int32_t)((r & 0xfffu) | ((r >> 12) << kIdBits));
+}
+__host__ __device__ inline uint32_t pack_local(int32_t local, int32_t w) {
+    return (uint32_t)local | (((uint32_t)w >> kIdBits) << 12);
+}
+
 struct Workspace {
     void *xbuf;          // second position buffer (double [n_vert][2])
     double *cap;         // per-cell (cA, cP) in the arithmetic type, sized for double
@@ -150,6 +189,28 @@ __host__ __device__ __forceinline__ T pdiff(T xa, T xb, int w, T L) {
     const T b = w > 0 ? xb - L : xb;
     return a - b;
 }
+
+// Edge length from its square, and length with inverse.  In FP32 they come
+// from the hardware square root and reciprocal square root (each within
+// about 1 ulp), which replace the much longer correctly rounded sequences
+// of sqrtf and 1/l; in FP64 from sqrt and a division.  Every kernel takes
+// its FP32 lengths from these, so all paths round alike.  A zero length
+// gives inverse 0.
+__device__ __forceinline__ float len_of(float l2) { return __builtin_amdgcn_sqrtf(l2); }
+__device__ __forceinline__ double len_of(double l2) { return sqrt(l2); }
+__device__ __forceinline__ void len_inv(float l2, float &l, float &inv) {
+    inv = l2 > 0.0f ? __builtin_amdgcn_rsqf(l2) : 0.0f;
+    l = l2 * inv;
+}
+__device__ __forceinline__ void len_inv(double l2, double &l, double &inv) {
+    l = sqrt(l2);
+    inv = l > 0.0 ? 1.0 / l : 0.0;
+}
+// num / |d| for |d|^2 = l2 > 0
+__device__ __forceinline__ float over_len(float num, float l2) {
+    return num * __builtin_amdgcn_rsqf(l2);
+}
+__device__ __forceinline__ double over_len(double num, double l2) { return num / sqrt(l2); }
 
 __device__ __forceinline__ double min_image(double d, double L) {
     return d - L * floor(d / L + 0.5);

@@ -251,6 +251,301 @@ __global__ __launch_bounds__(1024) void k_finish(VertexArgs a, int nblk) {
     finish_reductions<MODE>(a, nblk, sh, true);
 }
 
+// --------------------------------------------------------- fused evaluation
+// Heads of runs of equal keys in keys[per * tid, per * (tid + 1)) (INT_MAX
+// pads), compacted in order into out[0, cap); returns the number of
+// distinct keys (valid in every thread; may exceed cap, then out holds the
+// first cap).
+template <int PER>
+__device__ __forceinline__ int block_unique(const int32_t *keys, int32_t *out, int cap,
+                                            int32_t *scan) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int nh = 0;
+    for (int j = 0; j < PER; ++j) {
+        const int i = PER * tid + j;
+        const int32_t x = keys[i];
+        nh += (x != INT_MAX && (i == 0 || keys[i - 1] != x)) ? 1 : 0;
+    }
+    __syncthreads();
+    scan[tid] = nh;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        const int add = tid >= off ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
+    }
+    const int total = scan[nt - 1];
+    int o = scan[tid] - nh;
+    for (int j = 0; j < PER; ++j) {
+        const int i = PER * tid + j;
+        const int32_t x = keys[i];
+        if (x != INT_MAX && (i == 0 || keys[i - 1] != x)) {
+            if (o < cap) out[o] = x;
+            ++o;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ int lower_bound_lds(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One block per vertex tile builds the tile's local mesh: its distinct
+// cells (sorted, owner-tagged), their corner rows and the tile's star
+// neighbours as local references, and the halo of outside vertices they
+// reach.  Tiles whose halo or rows overflow the fixed slots are marked for
+// the global path.
+__global__ __launch_bounds__(kTileV) void k_tile_build(DevTissue t, TileTables tt) {
+    constexpr int NK = 4096;  // 3 kTileV neighbours + kCornerCap corners, padded
+    static_assert(3 * kTileV + kCornerCap <= NK, "halo candidate buffer");
+    __shared__ int32_t keys[NK];
+    __shared__ int32_t uniq[kTileCap];
+    __shared__ int32_t halo[kHaloCap];
+    __shared__ int32_t scan[kTileV];
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int nv = t.n_vert;
+    const int lo = tile * kTileV;
+    const int hi = min(nv, lo + kTileV);
+    const int v = lo + tid;
+    const bool live = v < nv;
+    int32_t c[3] = {INT_MAX, INT_MAX, INT_MAX}, w[3] = {0, 0, 0};
+    if (live) {
+        const int4 a4 = reinterpret_cast<const int4 *>(t.star)[v];  // {nb_0, nb_1, nb_2, c_0}
+        w[0] = a4.x;
+        w[1] = a4.y;
+        w[2] = a4.z;
+        for (int k = 0; k < 3; ++k) c[k] = t.star[star_cell_at(nv, k, v)];
+    }
+    // (1) the distinct cells around the tile's vertices
+    for (int k = 0; k < 3; ++k) keys[3 * tid + k] = c[k];
+    keys[3 * kTileV + tid] = INT_MAX;
+    __syncthreads();
+    block_bitonic(keys, 4 * kTileV);
+    const int nu = block_unique<4>(keys, uniq, kTileCap, scan);  // <= 3 kTileV
+    // (2) row starts: exclusive scan of the rows' lengths, cells 3 tid .. 3 tid + 2
+    int len[3], cid[3];
+    int sum = 0;
+    for (int j = 0; j < 3; ++j) {
+        const int i = 3 * tid + j;
+        cid[j] = i < nu ? uniq[i] : -1;
+        len[j] = i < nu ? t.nsides[cid[j]] : 0;
+        sum += len[j];
+    }
+    scan[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kTileV; off <<= 1) {
+        const int add = tid >= off ? scan[tid - off] : 0;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
+    }
+    const int ncorner = scan[kTileV - 1];
+    int start[3];
+    start[0] = scan[tid] - sum;
+    start[1] = start[0] + len[0];
+    start[2] = start[1] + len[1];
+    bool fallback = ncorner > kCornerCap;
+    // (3) the halo: neighbours and corners outside [lo, hi)
+    int nh = 0;
+    if (!fallback) {
+        __syncthreads();
+        for (int i = tid; i < NK; i += kTileV) keys[i] = INT_MAX;
+        __syncthreads();
+        for (int k = 0; k < 3; ++k) {
+            const int id = id_of(w[k]);
+            keys[3 * tid + k] = live && (id < lo || id >= hi) ? id : INT_MAX;
+        }
+        for (int j = 0; j < 3; ++j) {
+            if (cid[j] < 0) continue;
+            const int rb = t.row_ptr[cid[j]];
+            for (int k = 0; k < len[j]; ++k) {
+                const int id = id_of(t.corner[rb + k]);
+                keys[3 * kTileV + start[j] + k] = id < lo || id >= hi ? id : INT_MAX;
+            }
+        }
+        __syncthreads();
+        block_bitonic(keys, NK);
+        nh = block_unique<NK / kTileV>(keys, halo, kHaloCap, scan);
+        fallback = nh > kHaloCap;
+    }
+    // (4) the tables
+    int32_t *dst = tt.cells + (int64_t)tile * kTileCap;
+    for (int j = 0; j < 3; ++j) {
+        if (cid[j] < 0) continue;
+        const int v0 = id_of(t.corner[t.row_ptr[cid[j]]]);
+        dst[3 * tid + j] = v0 / kTileV == tile ? (int32_t)((uint32_t)cid[j] | 0x80000000u) : cid[j];
+    }
+    auto local_of = [&](int32_t wk) -> int {
+        const int id = id_of(wk);
+        return id >= lo && id < hi ? id - lo : kTileV + lower_bound_lds(halo, nh, id);
+    };
+    if (!fallback) {
+        for (int i = tid; i < nh; i += kTileV) tt.halo[(int64_t)tile * kHaloCap + i] = halo[i];
+        uint16_t *cs = tt.cstart + (int64_t)tile * kCstartPad;
+        uint16_t *co = tt.corners + (int64_t)tile * kCornerCap;
+        for (int j = 0; j < 3; ++j) {
+            if (cid[j] < 0) continue;
+            cs[3 * tid + j] = (uint16_t)start[j];
+            const int rb = t.row_ptr[cid[j]];
+            for (int k = 0; k < len[j]; ++k) {
+                const int32_t wk = t.corner[rb + k];
+                co[start[j] + k] = (uint16_t)pack_local(local_of(wk), wk);
+            }
+        }
+        if (tid == 0) cs[nu] = (uint16_t)ncorner;
+    }
+    if (tid == 0) tt.info[tile] = make_int4(nu, fallback ? 0 : nh, fallback ? 1 : 0, ncorner);
+    if (live) {
+        int lc = 0;
+        for (int k = 0; k < 3; ++k) lc |= lower_bound_lds(uniq, nu, c[k]) << (10 * k);
+        uint32_t nb[3] = {0u, 0u, 0u};
+        if (!fallback)
+            for (int k = 0; k < 3; ++k) nb[k] = pack_local(local_of(w[k]), w[k]);
+        const int e0 = t.star[star_edge_at(nv, 0, v)];
+        tt.fstar[v] = make_int4((int32_t)(nb[0] | (nb[1] << 16)), (int32_t)nb[2], lc, e0);
+        tt.fe[v] = t.star[star_edge_at(nv, 1, v)];
+        tt.fe[(int64_t)nv + v] = t.star[star_edge_at(nv, 2, v)];
+    }
+}
+
+// Energy and forces in one launch.  Each block takes one vertex tile: it
+// issues its vertices' edge-tension gathers, stages the positions of the
+// tile and its halo, the tile's corner rows and row starts in LDS, computes
+// (cA, cP) of the tile's cells there (cells on the tile border are computed
+// by every tile around them; the owner adds the cell energy), then forms
+// the forces from LDS.  The arithmetic is that of k_cell + k_vertex, so F is
+// bit-identical to the two-pass evaluation.  Tiles marked for the global
+// path read the star, the rows and the positions from global memory.
+template <typename PosT, typename M>
+__global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *__restrict__ X,
+                                                       PosT *__restrict__ out, DevParams<PosT> p,
+                                                       TileTables tt, VertexArgs a) {
+    using V2 = typename Vec2<PosT>::type;
+    __shared__ V2 sh_x[kTileV + kHaloCap];
+    __shared__ typename Vec2<M>::type sh_cap[kTileCap];
+    __shared__ uint4 sh_corner[kCornerCap / 8];
+    __shared__ uint16_t sh_cstart[kCstartPad];
+    __shared__ double sh[2 * (kTileV / 64)];
+    const int tid = threadIdx.x;
+    const int tile = xcd_block();
+    const int4 info = tt.info[tile];
+    const int nc = info.x, nh = info.y, ncorner = info.w;
+    const bool local = info.z == 0;
+    const int nv = t.n_vert;
+    const int v = tile * kTileV + tid;
+    const bool live = v < nv;
+    const PosT *Xl = reinterpret_cast<const PosT *>(sh_x);
+    const uint16_t *crn = reinterpret_cast<const uint16_t *>(sh_corner);
+    StarLoad<PosT, M> L;
+    int lc = 0;
+    if (live) {
+        const int4 f = tt.fstar[v];
+        lc = f.z;
+        L.e[0] = f.w;
+        L.e[1] = tt.fe[v];
+        L.e[2] = tt.fe[(int64_t)nv + v];
+        if (local) {
+            L.w[0] = unpack_local((uint32_t)f.x & 0xffffu);
+            L.w[1] = unpack_local((uint32_t)f.x >> 16);
+            L.w[2] = unpack_local((uint32_t)f.y);
+        } else {
+            const int4 s4 = reinterpret_cast<const int4 *>(t.star)[v];
+            L.w[0] = s4.x;
+            L.w[1] = s4.y;
+            L.w[2] = s4.z;
+            L.pi = ld2(X, v);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.q[k] = ld2(X, id_of(L.w[k]));
+        }
+        if (p.lam) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.lam[k] = p.lam[L.e[k]];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.lam[k] = p.lam_s;
+        }
+    }
+    // the thread's first cell (tiles rarely have more than kTileV cells)
+    const int32_t *cl = tt.cells + (int64_t)tile * kTileCap;
+    const int32_t x0 = tid < nc ? cl[tid] : 0;
+    if (local) {
+        if (live) sh_x[tid] = ld2(X, v);
+        const int32_t *hl = tt.halo + (int64_t)tile * kHaloCap;
+        for (int j = tid; j < nh; j += kTileV) sh_x[kTileV + j] = ld2(X, hl[j]);
+        const uint4 *src = reinterpret_cast<const uint4 *>(tt.corners + (int64_t)tile * kCornerCap);
+        for (int j = tid; j < (ncorner + 7) / 8; j += kTileV) sh_corner[j] = src[j];
+        const uint16_t *cs = tt.cstart + (int64_t)tile * kCstartPad;
+        for (int j = tid; j <= nc; j += kTileV) sh_cstart[j] = cs[j];
+    }
+    __syncthreads();
+    double ec = 0.0;
+    for (int i = tid; i < nc; i += kTileV) {
+        const int32_t x = i == tid ? x0 : cl[i];
+        const int c = x & 0x7fffffff;
+        PosT A, P;
+        if (local) {
+            const int rb = sh_cstart[i], n = (int)sh_cstart[i + 1] - rb;
+            cell_geom<PosT, PosT>(
+                t, Xl, n, [&](int k) { return unpack_local(crn[rb + k]); }, 0, A, P, false,
+                (PosT)0, (int32_t *)nullptr, (unsigned int *)nullptr);
+        } else {
+            const int rb = t.row_ptr[c], n = t.nsides[c];
+            cell_geom<PosT, PosT>(
+                t, X, n, [&](int k) { return t.corner[rb + k]; }, rb, A, P, false, (PosT)0,
+                (int32_t *)nullptr, (unsigned int *)nullptr);
+        }
+        const PosT ka = p.ka(c), kp = p.kp(c);
+        const PosT da = A - p.a0(c), dp = P - p.p0(c);
+        typename Vec2<M>::type cc;
+        cc.x = (M)((PosT)2 * ka * da);
+        cc.y = (M)((PosT)2 * kp * dp);
+        sh_cap[i] = cc;
+        if (x < 0 && a.E_out)
+            ec += (double)ka * (double)da * (double)da + (double)kp * (double)dp * (double)dp;
+    }
+    __syncthreads();
+    double el = 0.0, mf = 0.0;
+    if (live) {
+        if (local) {
+            L.pi = sh_x[tid];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L.q[k] = sh_x[id_of(L.w[k])];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.cc[k] = sh_cap[(lc >> (10 * k)) & 1023];
+        Star<PosT, M> s;
+        PosT xi, yi;
+        star_math<PosT, M>(t, L, s, xi, yi);
+        M fx, fy;
+        star_force<PosT, M>(s, fx, fy);
+        if (a.E_out)
+            el = 0.5 * ((double)s.lam[0] * (double)s.l[0] + (double)s.lam[1] * (double)s.l[1] +
+                        (double)s.lam[2] * (double)s.l[2]);
+        if (out) st2(out, v, (PosT)fx, (PosT)fy);
+        mf = fmax(fabs((double)fx), fabs((double)fy));
+        if (!(fx == fx) || !(fy == fy)) mf = INFINITY;
+    }
+    if (a.maxf_out || a.E_out) {
+        const double2 r = block_sum_max(el + ec, mf, sh);
+        __shared__ int s_last;
+        if (threadIdx.x == 0) {
+            a.part[blockIdx.x] = r;
+            s_last = a.finish ? last_block(&a.ctl->arrive) : 0;
+        }
+        __syncthreads();
+        if (s_last) finish_reductions<0>(a, gridDim.x, sh, false);
+    }
+}
+
 // ---------------------------------------------------------------------- T1
 template <typename PosT, typename M>
 __global__ __launch_bounds__(kBlock) void k_t1(DevTissue t, PosT *X, DevParams<PosT> p, M *cap,
@@ -872,6 +1167,37 @@ static void eval_impl(const DevTissue &t, const Workspace &w, const void *X, con
                        (PosT *)F, p, (const M *)w.cap, a);
     if (!a.finish && (E || maxf))
         hipLaunchKernelGGL((k_finish<0>), dim3(1), dim3(1024), 0, s, a, (int)gv);
+}
+
+template <typename PosT, typename M>
+static void eval_fused_impl(const DevTissue &t, const Workspace &w, const TileTables &tt,
+                            const void *X, const ParamsRaw &pr, double *E, void *F, double *maxf,
+                            hipStream_t s) {
+    auto p = dev_params<PosT>(pr);
+    const unsigned g = (unsigned)n_tiles_for(t.n_vert);
+    VertexArgs a{};
+    a.ctl = w.ctl + 1;
+    a.part = (double2 *)w.mpart;
+    a.finish = g <= (unsigned)kLastBlockMax;
+    a.E_out = E;
+    a.maxf_out = maxf;
+    hipLaunchKernelGGL((k_eval_fused<PosT, M>), dim3(g), dim3(kTileV), 0, s, t, (const PosT *)X,
+                       (PosT *)F, p, tt, a);
+    if (!a.finish && (E || maxf))
+        hipLaunchKernelGGL((k_finish<0>), dim3(1), dim3(1024), 0, s, a, (int)g);
+}
+
+void launch_eval_fused(const DevTissue &t, const Workspace &w, const TileTables &tt, int mode,
+                       const void *X, const ParamsRaw &p, double *E, void *F, double *maxf,
+                       hipStream_t s) {
+    if (mode == VTX_F32) eval_fused_impl<float, float>(t, w, tt, X, p, E, F, maxf, s);
+    else if (mode == VTX_F64) eval_fused_impl<double, double>(t, w, tt, X, p, E, F, maxf, s);
+    else eval_fused_impl<double, float>(t, w, tt, X, p, E, F, maxf, s);
+}
+
+void launch_tile_build(const DevTissue &t, const TileTables &tt, hipStream_t s) {
+    const int64_t g = n_tiles_for(t.n_vert);
+    if (g > 0) hipLaunchKernelGGL(k_tile_build, dim3((unsigned)g), dim3(kTileV), 0, s, t, tt);
 }
 
 void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X,

@@ -23,6 +23,10 @@ struct RelaxArgs {
 
 void launch_eval(const DevTissue &t, const Workspace &w, int mode, const void *X,
                  const ParamsRaw &p, double *E, void *F, double *maxf, hipStream_t s);
+void launch_eval_fused(const DevTissue &t, const Workspace &w, const TileTables &tt, int mode,
+                       const void *X, const ParamsRaw &p, double *E, void *F, double *maxf,
+                       hipStream_t s);
+void launch_tile_build(const DevTissue &t, const TileTables &tt, hipStream_t s);
 void launch_cell_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,
                       const ParamsRaw &p, void *coeffs, hipStream_t s);
 void launch_vertex_pass(const DevTissue &t, const Workspace &w, int mode, const void *X,

@@ -750,6 +750,65 @@ def test_split_passes_equal_full_evaluation(vtx, oracle):
     np.testing.assert_allclose(cf[:, 1], 2 * p.KP * (P_ - p.P0), rtol=1e-10, atol=1e-13)
 
 
+@pytest.mark.parametrize("mode", ["f32", "mixed", "f64"])
+def test_fused_evaluation_follows_topology(vtx, oracle, errlog, mode):
+    """The fused evaluation (one launch per 256-vertex tile) keeps its tile
+    tables in step with the topology: after T1 relaxations, single and
+    batched, its forces equal the two-pass evaluation bit for bit, its
+    energy equals the oracle's on the edited topology, and a graph captured
+    before the topology changed replays to the eager result."""
+    dt = vtx.pos_dtype(mode)
+    t, p = g.workload_single_10k(n_cell=2000, seed=213)
+    T = vtx.Tissue.from_tissue(t)
+    P = vtx.Params.from_numpy(p, dtype=dt)
+    cp, keep = P.to_c(dt, torch.device("cuda"))
+    Xd = _dev(t.X, dt)
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+    F = torch.empty_like(Xd)
+    mf = torch.empty((), dtype=torch.float64, device="cuda")
+    T.energy_forces_into(Xd, cp, E, F, mf, mode=mode)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        T.energy_forces_into(Xd, cp, E, F, mf, mode=mode)
+    torch.cuda.current_stream().wait_stream(s)
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        T.energy_forces_into(Xd, cp, E, F, mf, mode=mode)
+    r = T.relax(Xd, P, mode=mode, eta=3e-3, tol=1e-6, max_iter=3000, t1_enable=True, l_min=0.01)
+    assert r["n_t1"] > 0, r
+
+    def check(Ti, Xi, Pi, ti_p):
+        E1, F1, m1 = Ti.energy_forces(Xi, Pi, mode=mode, want_maxf=True)
+        cf = Ti.cell_coeffs(Xi, Pi, mode=mode)
+        F2, _ = Ti.vertex_forces(Xi, Pi, cf, mode=mode, want_maxf=True)
+        assert torch.equal(F1, F2)
+        assert m1.item() == F1.abs().max().item()
+        m = oracle.Mesh(Ti.topology(), Ti.n_vert, Ti.Lx, Ti.Ly)
+        Eo, _ = oracle.energy_forces(m, Xi.double().cpu().numpy(), ti_p)
+        return E1, F1, abs(E1.item() - Eo) / abs(Eo)
+
+    E1, F1, rel = check(T, Xd, P, p)
+    errlog(f"fused evaluation {mode} after T1 relaxation: energy against the oracle "
+           "(relative)", rel)
+    assert rel < {"f32": 1e-5, "mixed": 1e-6, "f64": 1e-12}[mode]
+    gr.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(F, F1) and E.item() == E1.item() and mf.item() == F1.abs().max().item()
+    # batched relaxation with T1, three tissues (one of them ragged: 301 cells)
+    rng = np.random.default_rng(214)
+    cases = [_batch_case(rng, n, P0) for n, P0 in ((301, 3.70), (700, 3.65), (1000, 3.72))]
+    Ts = [vtx.Tissue.from_tissue(tc) for tc, _ in cases]
+    Xs = [_dev(tc.X, dt) for tc, _ in cases]
+    Ps = [vtx.Params.from_numpy(pc, dtype=dt) for _, pc in cases]
+    res = vtx.Batch(Ts).relax(Xs, Ps, mode=mode, eta=3e-3, tol=1e-6, max_iter=3000,
+                              t1_enable=True, l_min=0.01)
+    assert sum(r["n_t1"] for r in res) > 0
+    for Ti, Xi, Pi, (_, pc) in zip(Ts, Xs, Ps, cases):
+        _, _, rel = check(Ti, Xi, Pi, pc)
+        assert rel < {"f32": 1e-5, "mixed": 1e-6, "f64": 1e-12}[mode]
+
+
 def test_batch_schedules_agree(vtx):
     """The persistent schedule (256 and 1024 threads per tissue), the grid
     schedule and the autotuned choice give the same relaxations."""
