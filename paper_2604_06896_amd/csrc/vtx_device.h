@@ -16,8 +16,10 @@ namespace vtx {
 // coordinates:  A = 1/2 sum_k r_{k-1} x r_k,  P = sum_k |r_k - r_{k-1}|.
 // When `det` is set, edges shorter than sqrt(lmin2) whose source id is below
 // the target id (one half-edge of each edge) are appended to `list` as the
-// global index of their source corner.
-template <typename PosT, typename M, typename CornerAt>
+// global index of their source corner.  NOIMG: every corner is known to
+// carry the zero image, and the periodic differences reduce to plain
+// subtractions (the same values).
+template <typename PosT, typename M, bool NOIMG = false, typename CornerAt>
 __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__restrict__ X,
                                           int n, CornerAt corner_at, int row_base, M &A, M &P,
                                           bool det, M lmin2, int32_t *list,
@@ -38,8 +40,8 @@ __device__ __forceinline__ void cell_geom(const DevTissue &t, const PosT *__rest
     int vprev = v0;
     auto step = [&](int k, int32_t wk, typename Vec2<PosT>::type qk) {
         const int v = id_of(wk);
-        const M rx = (M)pdiff<PosT>(qk.x, p0.x, ox_of(wk), Lx);
-        const M ry = (M)pdiff<PosT>(qk.y, p0.y, oy_of(wk), Ly);
+        const M rx = (M)pdiff<PosT>(qk.x, p0.x, NOIMG ? 0 : ox_of(wk), Lx);
+        const M ry = (M)pdiff<PosT>(qk.y, p0.y, NOIMG ? 0 : oy_of(wk), Ly);
         const M dx = rx - px, dy = ry - py;
         const M l2 = dx * dx + dy * dy;
         a += px * ry - py * rx;
@@ -131,7 +133,8 @@ __device__ __forceinline__ void star_gather(const PosT *__restrict__ X, const De
     }
 }
 
-template <typename PosT, typename M>
+// NOIMG: the three neighbours are known to carry the zero image.
+template <typename PosT, typename M, bool NOIMG = false>
 __device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<PosT, M> &L,
                                           Star<PosT, M> &s, PosT &xi, PosT &yi) {
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
@@ -140,8 +143,8 @@ __device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<Pos
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         s.nb[k] = id_of(L.w[k]);
-        s.dx[k] = (M)pdiff<PosT>(L.q[k].x, L.pi.x, ox_of(L.w[k]), Lx);
-        s.dy[k] = (M)pdiff<PosT>(L.q[k].y, L.pi.y, oy_of(L.w[k]), Ly);
+        s.dx[k] = (M)pdiff<PosT>(L.q[k].x, L.pi.x, NOIMG ? 0 : ox_of(L.w[k]), Lx);
+        s.dy[k] = (M)pdiff<PosT>(L.q[k].y, L.pi.y, NOIMG ? 0 : oy_of(L.w[k]), Ly);
         s.cA[k] = L.cc[k].x;
         s.cP[k] = L.cc[k].y;
         s.lam[k] = (M)L.lam[k];

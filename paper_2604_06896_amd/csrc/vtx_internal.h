@@ -115,13 +115,15 @@ struct LoopCtl {
 // mesh.  Vertex tile b is the kTileV consecutive vertices from b * kTileV.
 // Its cells (every cell around one of its vertices, at most kTileCap) are
 // listed in slot b of `cells`, bit 31 set where tile b owns the cell (holds
-// its corner 0) so that each cell energy is counted once.  Its halo lists
+// its corner 0) so that each cell energy is counted once, bit 30 where the
+// cell crosses the box (a corner carries a nonzero image).  Its halo lists
 // the other vertices those cells and the tile's edges reach.  Local vertex
 // index j < kTileV is vertex b * kTileV + j, j >= kTileV is halo[j - kTileV].
 // Corner rows and star neighbours are stored as 16-bit local references:
 // local index in the low 12 bits, the periodic image (as in pack_id) in the
-// top 4.  Per vertex, `fstar` = {nb_0 | nb_1 << 16, nb_2, local cells (10
-// bits each), e_0} and `fe` = [2][n_vert] {e_1, e_2}.  A tile whose halo or
+// top 4.  Per vertex, `fstar` = {nb_0 | nb_1 << 16, nb_2 | (a neighbour
+// carries a nonzero image) << 16, local cells (10 bits each), e_0} and
+// `fe` = [2][n_vert] {e_1, e_2}.  A tile whose halo or
 // corner rows do not fit (info.z = 1) is evaluated from the global star and
 // rows instead.  Everything is derived from the star and the corner rows and
 // rebuilt whenever the topology changes.
@@ -130,6 +132,9 @@ constexpr int kTileCap = 3 * kTileV;        // cells per tile
 constexpr int kHaloCap = 768;               // halo vertices per tile
 constexpr int kCornerCap = 2048;            // corner references per tile
 constexpr int kCstartPad = kTileCap + 8;    // row starts per tile (uint16)
+constexpr uint32_t kZeroImage = 5u;           // image field of pack_id(id, 0, 0)
+constexpr uint32_t kCellOwner = 0x80000000u;  // cells[]: the tile owns the cell
+constexpr uint32_t kCellImage = 0x40000000u;  // cells[]: a corner has a nonzero image
 struct TileTables {
     int32_t *cells;     // [n_tiles][kTileCap]
     int4 *info;         // [n_tiles] {cells, halo vertices, global fallback, corners}

@@ -300,7 +300,7 @@ __device__ __forceinline__ int lower_bound_lds(const int32_t *a, int n, int32_t 
 }
 
 // One block per vertex tile builds the tile's local mesh: its distinct
-// cells (sorted, owner-tagged), their corner rows and the tile's star
+// cells (owner-tagged, ordered by side count), their corner rows and the tile's star
 // neighbours as local references, and the halo of outside vertices they
 // reach.  Tiles whose halo or rows overflow the fixed slots are marked for
 // the global path.
@@ -308,7 +308,10 @@ __global__ __launch_bounds__(kTileV) void k_tile_build(DevTissue t, TileTables t
     constexpr int NK = 4096;  // 3 kTileV neighbours + kCornerCap corners, padded
     static_assert(3 * kTileV + kCornerCap <= NK, "halo candidate buffer");
     __shared__ int32_t keys[NK];
-    __shared__ int32_t uniq[kTileCap];
+    __shared__ int32_t uniq[kTileCap];  // distinct cells by id
+    __shared__ int32_t ord[kTileCap];   // the same cells by side count (then id)
+    __shared__ int32_t perm[kTileCap];  // position in ord of uniq[i]
+    __shared__ int32_t oimg[kTileCap];  // ord[r] has a corner with a nonzero image
     __shared__ int32_t halo[kHaloCap];
     __shared__ int32_t scan[kTileV];
     const int tile = blockIdx.x, tid = threadIdx.x;
@@ -331,12 +334,35 @@ __global__ __launch_bounds__(kTileV) void k_tile_build(DevTissue t, TileTables t
     __syncthreads();
     block_bitonic(keys, 4 * kTileV);
     const int nu = block_unique<4>(keys, uniq, kTileCap, scan);  // <= 3 kTileV
+    // (1b) cells ordered by (crosses the box, side count), so that the lanes
+    // of a wave walk rows of equal length and most waves need no images
+    for (int i = tid; i < 4 * kTileV; i += kTileV) {
+        int key = INT_MAX;
+        if (i < nu) {
+            const int cc = uniq[i];
+            const int ns = t.nsides[cc], rb = t.row_ptr[cc];
+            int img = 0;
+            for (int k = 0; k < ns; ++k)
+                img |= ((uint32_t)t.corner[rb + k] >> kIdBits) != kZeroImage ? 1 : 0;
+            key = (((img << 10) | min(ns, 1023)) << 10) | i;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    block_bitonic(keys, 4 * kTileV);
+    for (int r = tid; r < nu; r += kTileV) {
+        const int i = keys[r] & 1023;
+        ord[r] = uniq[i];
+        perm[i] = r;
+        oimg[r] = (keys[r] >> 20) & 1;
+    }
+    __syncthreads();
     // (2) row starts: exclusive scan of the rows' lengths, cells 3 tid .. 3 tid + 2
     int len[3], cid[3];
     int sum = 0;
     for (int j = 0; j < 3; ++j) {
         const int i = 3 * tid + j;
-        cid[j] = i < nu ? uniq[i] : -1;
+        cid[j] = i < nu ? ord[i] : -1;
         len[j] = i < nu ? t.nsides[cid[j]] : 0;
         sum += len[j];
     }
@@ -382,7 +408,9 @@ __global__ __launch_bounds__(kTileV) void k_tile_build(DevTissue t, TileTables t
     for (int j = 0; j < 3; ++j) {
         if (cid[j] < 0) continue;
         const int v0 = id_of(t.corner[t.row_ptr[cid[j]]]);
-        dst[3 * tid + j] = v0 / kTileV == tile ? (int32_t)((uint32_t)cid[j] | 0x80000000u) : cid[j];
+        uint32_t e = (uint32_t)cid[j] | (oimg[3 * tid + j] ? kCellImage : 0u);
+        if (v0 / kTileV == tile) e |= kCellOwner;
+        dst[3 * tid + j] = (int32_t)e;
     }
     auto local_of = [&](int32_t wk) -> int {
         const int id = id_of(wk);
@@ -406,12 +434,15 @@ __global__ __launch_bounds__(kTileV) void k_tile_build(DevTissue t, TileTables t
     if (tid == 0) tt.info[tile] = make_int4(nu, fallback ? 0 : nh, fallback ? 1 : 0, ncorner);
     if (live) {
         int lc = 0;
-        for (int k = 0; k < 3; ++k) lc |= lower_bound_lds(uniq, nu, c[k]) << (10 * k);
+        for (int k = 0; k < 3; ++k) lc |= perm[lower_bound_lds(uniq, nu, c[k])] << (10 * k);
         uint32_t nb[3] = {0u, 0u, 0u};
         if (!fallback)
             for (int k = 0; k < 3; ++k) nb[k] = pack_local(local_of(w[k]), w[k]);
+        uint32_t vimg = 0;
+        for (int k = 0; k < 3; ++k) vimg |= ((uint32_t)w[k] >> kIdBits) != kZeroImage ? 1u : 0u;
         const int e0 = t.star[star_edge_at(nv, 0, v)];
-        tt.fstar[v] = make_int4((int32_t)(nb[0] | (nb[1] << 16)), (int32_t)nb[2], lc, e0);
+        tt.fstar[v] = make_int4((int32_t)(nb[0] | (nb[1] << 16)), (int32_t)(nb[2] | (vimg << 16)),
+                                lc, e0);
         tt.fe[v] = t.star[star_edge_at(nv, 1, v)];
         tt.fe[(int64_t)nv + v] = t.star[star_edge_at(nv, 2, v)];
     }
@@ -447,6 +478,7 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
     const uint16_t *crn = reinterpret_cast<const uint16_t *>(sh_corner);
     StarLoad<PosT, M> L;
     int lc = 0;
+    uint32_t vimg = 0;
     if (live) {
         const int4 f = tt.fstar[v];
         lc = f.z;
@@ -456,7 +488,8 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
         if (local) {
             L.w[0] = unpack_local((uint32_t)f.x & 0xffffu);
             L.w[1] = unpack_local((uint32_t)f.x >> 16);
-            L.w[2] = unpack_local((uint32_t)f.y);
+            L.w[2] = unpack_local((uint32_t)f.y & 0xffffu);
+            vimg = ((uint32_t)f.y >> 16) & 1u;
         } else {
             const int4 s4 = reinterpret_cast<const int4 *>(t.star)[v];
             L.w[0] = s4.x;
@@ -490,13 +523,18 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
     double ec = 0.0;
     for (int i = tid; i < nc; i += kTileV) {
         const int32_t x = i == tid ? x0 : cl[i];
-        const int c = x & 0x7fffffff;
+        const int c = (int)((uint32_t)x & kIdMask);
         PosT A, P;
         if (local) {
             const int rb = sh_cstart[i], n = (int)sh_cstart[i + 1] - rb;
-            cell_geom<PosT, PosT>(
-                t, Xl, n, [&](int k) { return unpack_local(crn[rb + k]); }, 0, A, P, false,
-                (PosT)0, (int32_t *)nullptr, (unsigned int *)nullptr);
+            auto corner_at = [&](int k) { return unpack_local(crn[rb + k]); };
+            // waves whose cells all lie inside the box take plain differences
+            if (__builtin_amdgcn_ballot_w64(((uint32_t)x & kCellImage) != 0) != 0)
+                cell_geom<PosT, PosT, false>(t, Xl, n, corner_at, 0, A, P, false, (PosT)0,
+                                             (int32_t *)nullptr, (unsigned int *)nullptr);
+            else
+                cell_geom<PosT, PosT, true>(t, Xl, n, corner_at, 0, A, P, false, (PosT)0,
+                                            (int32_t *)nullptr, (unsigned int *)nullptr);
         } else {
             const int rb = t.row_ptr[c], n = t.nsides[c];
             cell_geom<PosT, PosT>(
@@ -524,14 +562,17 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
         for (int k = 0; k < 3; ++k) L.cc[k] = sh_cap[(lc >> (10 * k)) & 1023];
         Star<PosT, M> s;
         PosT xi, yi;
-        star_math<PosT, M>(t, L, s, xi, yi);
+        if (__builtin_amdgcn_ballot_w64(vimg != 0u || !local) != 0)
+            star_math<PosT, M, false>(t, L, s, xi, yi);
+        else
+            star_math<PosT, M, true>(t, L, s, xi, yi);
         M fx, fy;
         star_force<PosT, M>(s, fx, fy);
+        // half of each edge's line energy, summed in the arithmetic type
         if (a.E_out)
-            el = 0.5 * ((double)s.lam[0] * (double)s.l[0] + (double)s.lam[1] * (double)s.l[1] +
-                        (double)s.lam[2] * (double)s.l[2]);
+            el = 0.5 * (double)(s.lam[0] * s.l[0] + s.lam[1] * s.l[1] + s.lam[2] * s.l[2]);
         if (out) st2(out, v, (PosT)fx, (PosT)fy);
-        mf = fmax(fabs((double)fx), fabs((double)fy));
+        mf = (double)fmax(fabs(fx), fabs(fy));
         if (!(fx == fx) || !(fy == fy)) mf = INFINITY;
     }
     if (a.maxf_out || a.E_out) {
