@@ -5,16 +5,20 @@ Headline workload (the force-kernel throughput case): one periodic Voronoi
 tissue of 10^6 cells (uniform-random seeds, box side 1000; 2e6 3-valent
 vertices, 3e6 edges), FP32 positions, K_A = A0 = K_P = 1, P0 = 3.75,
 per-edge lambda ~ U[0.05, 0.15], fixed topology.  One step is one energy +
-force evaluation (cell pass + vertex pass + deterministic FP64 energy and
-max-force reductions), replayed from captured graphs with the inputs
-resident in HBM; exactly --warmup untimed and --steps timed evaluations.
+force evaluation (the fused tile kernel, which forms the cell coefficients
+in LDS and the forces from them, then a one-block finish of the
+deterministic FP64 energy and max-force sums), replayed from captured
+graphs with the inputs resident in HBM; exactly --warmup untimed and
+--steps timed evaluations.
 
 Printed: one JSON line with the whole-job vertex-force evaluations per
-second; the roofline of the dominant kernel (the vertex pass, timed alone
-with HIP events on the stream it is launched on) against its algorithmic
-floor of 34 bytes per vertex (positions in, forces out, one 3-neighbour
-list, each edge tension once), warm (working set served partly from the
-256 MB Infinity Cache) and cold (after a 512 MiB write); the oracle timed on
+second; the roofline of the dominant kernel (the fused evaluation kernel,
+timed alone with HIP events on the stream it is launched on) against the
+algorithmic floor of an evaluation, 34 bytes per vertex (positions in,
+forces out, one 3-neighbour list, each edge tension once), warm (working set
+served partly from the 256 MB Infinity Cache) and cold (after a 512 MiB
+write), with the two-pass kernels (cell pass, vertex pass) timed the same
+way for reference; the oracle timed on
 the host cores (one thread and all cores of the box's share); and, unless
 --no-secondary, the other workloads: the 100-cell and 10^4-cell single
 relaxations, the 512-tissue batched relaxation and the 64-tissue batched
@@ -36,15 +40,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "vertex-force evals/s; param-gradients/s (batched adjoint vs plain) at 1e-6 tol"
 FLOOR_B_PER_VERTEX = 34   # positions in 8 + forces out 8 + 3-neighbour list 12 + lambda 6
-COUNTERS = os.path.join(ROOT, "profiles", "vertex_pass_1m_cells_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "eval_fused_1m_cells_counters.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def fused_design_bytes(n_vert, n_edge, ts):
+    """Bytes the fused evaluation kernel must move at least once (FP32), from
+    the tile tables' layout `ts` (Tissue.tile_stats())."""
+    return (ts["tiles"] * 16                 # per-tile counts
+            + ts["cells"] * 4                # tile cell lists
+            + ts["halo"] * (4 + 8)           # halo ids and their positions
+            + (ts["cells"] + ts["tiles"]) * 2  # row starts
+            + ts["corners"] * 2              # corner references
+            + n_vert * (16 + 8)              # local star + edge ids
+            + n_vert * 8                     # own position
+            + n_edge * 4                     # lambda of every edge
+            + n_vert * 8)                    # forces written
+
+
 def design_bytes(n_vert, n_cell, n_edge, n_he):
-    """Bytes each pass of the current layout must move at least once (FP32)."""
+    """Bytes each pass of the two-pass layout must move at least once (FP32)."""
     vertex = (n_vert * 8          # own position
               + n_vert * 36       # star: 3 neighbour ids, 3 cell ids, 3 edge ids
               + n_cell * 8        # (cA, cP) of every cell
@@ -58,22 +76,27 @@ def design_bytes(n_vert, n_cell, n_edge, n_he):
     return vertex, cell
 
 
+KERNEL_SOURCES = ["include/vtx.h", "paper_2604_06896_amd/csrc/vtx_kernels.hip",
+                  "paper_2604_06896_amd/csrc/vtx_device.h",
+                  "paper_2604_06896_amd/csrc/vtx_internal.h",
+                  "paper_2604_06896_amd/csrc/vtx_launch.h"]
+
+
 def kernel_source_sha():
-    """Hash of the HIP sources, to tell whether committed counters still
-    describe the kernels that run."""
+    """Hash of the sources the evaluation kernels are compiled from, to tell
+    whether committed counters still describe the kernels that run."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2604_06896_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
 def read_traffic(path, sha):
-    """HBM bytes per vertex-pass launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
-    None if the summary is missing or was taken on other kernel sources."""
+    """HBM bytes per fused-evaluation launch from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel
+    calibration), or None if the summary is missing or was taken on other
+    kernel sources."""
     vals = {}
     try:
         with open(path) as f:
@@ -86,9 +109,9 @@ def read_traffic(path, sha):
     if vals.get("kernel_source_sha") != sha:
         return None, "counters taken on other kernel sources"
     try:
-        return float(vals["vertex_pass_bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE"
+        return float(vals["fused_eval_bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE"
     except (KeyError, ValueError):
-        return None, "no vertex-pass figure in the counter summary"
+        return None, "no fused-evaluation figure in the counter summary"
 
 
 # --------------------------------------------------------------- CPU baseline
@@ -382,8 +405,10 @@ def main():
     log(f"{steps} evaluations in {ms:.3f} ms (wall {wall * 1e3:.2f} ms): "
         f"{ms / steps * 1e3:.2f} us/eval, E = {E.item():.6f}, max|F| = {mf.item():.4f}")
 
-    # ---- dominant kernel alone: vertex pass (and cell pass), HIP events on
-    # the stream they are launched on (torch's current stream)
+    # ---- dominant kernel alone: the fused evaluation (forces only: no
+    # energy or max-force sums, hence no finish launch), then the two-pass
+    # kernels for reference; HIP events on the stream they are launched on
+    # (torch's current stream)
     coeffs = T.cell_coeffs(X, P, mode="f32")
     R = max(G, (args.kernel_reps // G) * G)
 
@@ -400,22 +425,27 @@ def main():
         return a.elapsed_time(b) / R
 
     F2 = torch.empty_like(X)
+    fused = lambda: T.energy_forces_into(X, cp, None, F2, None, mode="f32")  # noqa: E731
+    f_ms = timed_graph(fused)
     v_ms = timed_graph(lambda: T.vertex_forces_into(X, cp, coeffs, F2, mode="f32"))
     c_ms = timed_graph(lambda: V.lib().vtx_cell_coeffs(T.handle, V.F32, V._ptr(X), V.C.byref(cp),
                                                        V._ptr(coeffs), V._stream()))
+    ts = T.tile_stats()
+    fb = fused_design_bytes(t.n_vert, t.n_edge, ts)
     vb, cb = design_bytes(t.n_vert, t.n_cell, t.n_edge, t.n_he)
     floor = FLOOR_B_PER_VERTEX * t.n_vert
-    log(f"vertex pass {v_ms * 1e3:.2f} us ({floor / v_ms / 1e6:.0f} GB/s of the 34 B/vertex "
-        f"floor, {vb / v_ms / 1e6:.0f} GB/s of its design bytes), cell pass {c_ms * 1e3:.2f} us "
-        f"({cb / c_ms / 1e6:.0f} GB/s)")
+    log(f"fused evaluation kernel {f_ms * 1e3:.2f} us ({floor / f_ms / 1e6:.0f} GB/s of the "
+        f"34 B/vertex floor, {fb / f_ms / 1e6:.0f} GB/s of its design bytes, "
+        f"{fb / t.n_vert:.1f} B/vertex; tiles {ts})")
+    log(f"two-pass reference: vertex pass {v_ms * 1e3:.2f} us, cell pass {c_ms * 1e3:.2f} us")
     sha = kernel_source_sha()
     traffic, traffic_src = read_traffic(COUNTERS, sha)
 
     # ---- cold caches: 512 MiB written between evaluations (not timed), so
-    # that nothing of the ~180 MB an evaluation touches is left in the
+    # that nothing of the ~150 MB an evaluation touches is left in the
     # 256 MB Infinity Cache or the L2s
     g1 = capture(one_eval, 1)
-    gv1 = capture(lambda: T.vertex_forces_into(X, cp, coeffs, F2, mode="f32"), 1)
+    gf1 = capture(fused, 1)
     flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
 
     def cold(gr, n):
@@ -430,33 +460,37 @@ def main():
         return sorted(a.elapsed_time(b) for a, b in evs)[n // 2]  # median, ms
 
     cold_eval_ms = cold(g1, args.cold_reps)
-    cold_v_ms = cold(gv1, args.cold_reps)
-    del flush, g1, gv1
-    log(f"cold caches: evaluation {cold_eval_ms * 1e3:.2f} us, vertex pass {cold_v_ms * 1e3:.2f} "
-        f"us ({floor / cold_v_ms / 1e6:.0f} GB/s of the floor)")
+    cold_f_ms = cold(gf1, args.cold_reps)
+    del flush, g1, gf1
+    log(f"cold caches: evaluation {cold_eval_ms * 1e3:.2f} us, fused kernel {cold_f_ms * 1e3:.2f} "
+        f"us ({floor / cold_f_ms / 1e6:.0f} GB/s of the floor)")
 
     roofline = {
-        "bound": "hbm", "kernel": "k_vertex (vertex pass)",
-        "achieved": floor / v_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": floor / v_ms / 1e6 / HBM_PEAK_GBS, "traffic": traffic,
+        "bound": "hbm", "kernel": "k_eval_fused (the whole evaluation: cell coefficients in "
+                                  "LDS, then forces)",
+        "achieved": floor / f_ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": floor / f_ms / 1e6 / HBM_PEAK_GBS, "traffic": traffic,
         "bytes_per_launch": floor,
-        "bytes_basis": "algorithmic floor, 34 B per vertex: positions in 8, forces out 8, one "
-                       "3-neighbour list 12, each edge tension once 6",
-        "us_per_launch": v_ms * 1e3,
-        "timing": "warm: launches back to back, the ~180 MB working set partly served from the "
-                  "256 MB Infinity Cache",
+        "bytes_basis": "algorithmic floor of an evaluation, 34 B per vertex: positions in 8, "
+                       "forces out 8, one 3-neighbour list 12, each edge tension once 6",
+        "us_per_launch": f_ms * 1e3,
+        "timing": "warm: launches back to back, the working set partly served from the 256 MB "
+                  "Infinity Cache; forces only (the energy and max-force sums add a one-block "
+                  "finish launch, included in ms_per_step)",
         "traffic_source": traffic_src,
         "traffic_over_floor": traffic / floor if traffic else None,
-        "design": {"bytes_per_launch": vb, "achieved": vb / v_ms / 1e6,
-                   "frac": vb / v_ms / 1e6 / HBM_PEAK_GBS,
-                   "basis": "the current layout's bytes, each array once: 62 B per vertex"},
-        "cold_caches": {"vertex_pass_us": cold_v_ms * 1e3,
-                        "achieved": floor / cold_v_ms / 1e6,
-                        "frac": floor / cold_v_ms / 1e6 / HBM_PEAK_GBS,
-                        "design_frac": vb / cold_v_ms / 1e6 / HBM_PEAK_GBS,
+        "design": {"bytes_per_launch": fb, "bytes_per_vertex": fb / t.n_vert,
+                   "achieved": fb / f_ms / 1e6, "frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
+                   "basis": "the tile tables' bytes, each array once", "tile_stats": ts},
+        "cold_caches": {"fused_kernel_us": cold_f_ms * 1e3,
+                        "achieved": floor / cold_f_ms / 1e6,
+                        "frac": floor / cold_f_ms / 1e6 / HBM_PEAK_GBS,
+                        "design_frac": fb / cold_f_ms / 1e6 / HBM_PEAK_GBS,
                         "evaluation_us": cold_eval_ms * 1e3},
-        "cell_pass": {"us_per_launch": c_ms * 1e3, "design_bytes_per_launch": cb,
-                      "achieved": cb / c_ms / 1e6, "frac": cb / c_ms / 1e6 / HBM_PEAK_GBS},
+        "two_pass_reference": {
+            "vertex_pass_us": v_ms * 1e3, "vertex_pass_design_bytes": vb,
+            "cell_pass_us": c_ms * 1e3, "cell_pass_design_bytes": cb,
+            "vertex_pass_floor_frac": floor / v_ms / 1e6 / HBM_PEAK_GBS},
         "kernel_source_sha": sha,
     }
     del F2, coeffs

@@ -175,6 +175,14 @@ int vtx_tissue_destroy(vtx_tissue t);
 /* Sizes of a tissue (any pointer may be NULL). */
 int vtx_tissue_sizes(vtx_tissue t, int64_t *n_vert, int64_t *n_cell, int64_t *n_edge,
                      int64_t *n_he);
+/* Layout of the fused evaluation's tile tables (a diagnostic): stats[0] =
+ * vertex tiles (256 vertices each), stats[1] = cells listed over all tiles
+ * (a border cell is listed by every tile around it), stats[2] = halo
+ * vertices over all tiles, stats[3] = corner references over all tiles,
+ * stats[4] = tiles evaluated from global memory because their halo or rows
+ * overflow the fixed slots.  stats: host int64_t[5].  Synchronises the
+ * device. */
+int vtx_tissue_tile_stats(vtx_tissue t, int64_t *stats);
 /* Copy the current half-edge table (it changes under T1) to host memory
  * [n_he][8].  Synchronises the device. */
 int vtx_tissue_get_topology(vtx_tissue t, int32_t *he_out);

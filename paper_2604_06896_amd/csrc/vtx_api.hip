@@ -503,6 +503,24 @@ int vtx_tissue_sizes(vtx_tissue t, int64_t *n_vert, int64_t *n_cell, int64_t *n_
     return VTX_OK;
 }
 
+int vtx_tissue_tile_stats(vtx_tissue t, int64_t *stats) {
+    if (!t || !stats) return fail(VTX_E_ARG, "null argument");
+    const int64_t nt = n_tiles_for(t->n_vert);
+    std::vector<int4> info((size_t)nt);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(info.data(), t->tiles.info, sizeof(int4) * (size_t)nt,
+                     hipMemcpyDeviceToHost));
+    for (int k = 0; k < 5; ++k) stats[k] = 0;
+    stats[0] = nt;
+    for (const int4 &i : info) {
+        stats[1] += i.x;
+        stats[2] += i.y;
+        stats[3] += i.w;
+        stats[4] += i.z;
+    }
+    return VTX_OK;
+}
+
 int vtx_tissue_get_topology(vtx_tissue t, int32_t *he_out) {
     if (!t || !he_out) return fail(VTX_E_ARG, "null argument");
     HIPCHK(hipDeviceSynchronize());

@@ -84,6 +84,7 @@ def lib():
         L.vtx_tissue_create.argtypes = [vp, i64, i64, i64, d, d, P(vp)]
         L.vtx_tissue_destroy.argtypes = [vp]
         L.vtx_tissue_sizes.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
+        L.vtx_tissue_tile_stats.argtypes = [vp, P(i64)]
         L.vtx_tissue_get_topology.argtypes = [vp, vp]
         L.vtx_tissue_set_topology.argtypes = [vp, vp]
         L.vtx_energy_forces.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
@@ -215,6 +216,13 @@ class Tissue:
     @property
     def handle(self):
         return self._h
+
+    def tile_stats(self):
+        """Layout of the fused evaluation's tile tables: tiles, cells listed,
+        halo vertices, corner references, tiles on the global path."""
+        out = (C.c_int64 * 5)()
+        _check(lib().vtx_tissue_tile_stats(self._h, out))
+        return dict(zip(("tiles", "cells", "halo", "corners", "global_tiles"), list(out)))
 
     # -------------------------------------------------------- topology
     def topology(self):
