@@ -289,6 +289,16 @@ __device__ __forceinline__ double wave_max(double v) {
                   nanmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
+// Max over the wave of values that are never NaN (no NaN checks).
+__device__ __forceinline__ double wave_max_plain(double v) {
+    v = fmax(v, dpp_f64<kDppXor1>(v));
+    v = fmax(v, dpp_f64<kDppXor2>(v));
+    v = fmax(v, dpp_f64<kDppHalfMirror>(v));
+    v = fmax(v, dpp_f64<kDppMirror>(v));
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+                fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // Block-wide sum of a double (fixed order: deterministic for a fixed block size).
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     v = wave_sum(v);

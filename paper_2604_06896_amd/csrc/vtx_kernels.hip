@@ -547,8 +547,9 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
         cc.x = (M)((PosT)2 * ka * da);
         cc.y = (M)((PosT)2 * kp * dp);
         sh_cap[i] = cc;
-        if (x < 0 && a.E_out)
-            ec += (double)ka * (double)da * (double)da + (double)kp * (double)dp * (double)dp;
+        // the cell energy in the type of the positions (FP64 in the FP64
+        // and MIXED modes, where this equals the two-pass kernel's sum)
+        if (x < 0 && a.E_out) ec += (double)(ka * da * da + kp * dp * dp);
     }
     __syncthreads();
     double el = 0.0, mf = 0.0;
@@ -576,14 +577,31 @@ __global__ __launch_bounds__(kTileV) void k_eval_fused(DevTissue t, const PosT *
         if (!(fx == fx) || !(fy == fy)) mf = INFINITY;
     }
     if (a.maxf_out || a.E_out) {
-        const double2 r = block_sum_max(el + ec, mf, sh);
-        __shared__ int s_last;
-        if (threadIdx.x == 0) {
-            a.part[blockIdx.x] = r;
-            s_last = a.finish ? last_block(&a.ctl->arrive) : 0;
-        }
+        // The block's sums: every thread leaves (energy, max |F|) in the
+        // corner staging area (not read after the cell phase) and wave 0
+        // adds them, four per lane in fixed order, then across the wave.
+        // max |F| is never NaN here (a NaN force was mapped to +inf).
+        static_assert(2 * kTileV * sizeof(double) <= sizeof(sh_corner), "tail sums");
+        double *se = reinterpret_cast<double *>(sh_corner);
+        double *sm = se + kTileV;
+        se[tid] = el + ec;
+        sm[tid] = mf;
         __syncthreads();
-        if (s_last) finish_reductions<0>(a, gridDim.x, sh, false);
+        __shared__ int s_last;
+        if (tid < 64) {
+            double e = ((se[tid] + se[tid + 64]) + se[tid + 128]) + se[tid + 192];
+            double m = fmax(fmax(sm[tid], sm[tid + 64]), fmax(sm[tid + 128], sm[tid + 192]));
+            e = wave_sum(e);
+            m = wave_max_plain(m);
+            if (tid == 0) {
+                a.part[blockIdx.x] = double2{e, m};
+                s_last = a.finish ? last_block(&a.ctl->arrive) : 0;
+            }
+        }
+        if (a.finish) {  // small grids: the last block finishes the scalars
+            __syncthreads();
+            if (s_last) finish_reductions<0>(a, gridDim.x, sh, false);
+        }
     }
 }
 
