@@ -545,7 +545,11 @@ int vtx_tissue_set_topology(vtx_tissue t, const int32_t *he) {
         (rc = upload_into(d.nsides, S.nsides)) || (rc = upload_into(d.cell_he, S.cell_he)) ||
         (rc = upload_into(d.star, S.star)) || (rc = upload_into(d.star_he, S.star_he)))
         return rc;
-    return vtx::tissue_topology_changed(t, nullptr);
+    // synchronous like the uploads: the tables are complete on return, for
+    // callers on any stream
+    if ((rc = vtx::tissue_topology_changed(t, nullptr))) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    return VTX_OK;
 }
 
 int vtx_energy_forces(vtx_tissue t, int32_t mode, const void *X, const vtx_params *p,

@@ -809,6 +809,52 @@ def test_fused_evaluation_follows_topology(vtx, oracle, errlog, mode):
         assert rel < {"f32": 1e-5, "mixed": 1e-6, "f64": 1e-12}[mode]
 
 
+@pytest.mark.parametrize("mode", ["f32", "mixed", "f64"])
+def test_fused_evaluation_global_path_tiles(vtx, oracle, errlog, mode):
+    """Tiles whose halo or corner rows overflow their fixed slots take the
+    fused kernel's global-memory path.  Shuffled vertex ids scatter each
+    tile over the box, which sends every tile there; shuffling only the
+    second half mixes both kinds in one launch.  The forces equal the two
+    passes bit for bit and the energy and forces the oracle's."""
+    dt = vtx.pos_dtype(mode)
+    t, p = g.workload_single_10k(n_cell=3000, seed=215)
+    rng = np.random.default_rng(216)
+    nv = t.n_vert
+    for part in ("all", "half"):
+        perm = np.arange(nv)
+        if part == "all":
+            perm = rng.permutation(nv)
+        else:
+            perm[nv // 2:] = nv // 2 + rng.permutation(nv - nv // 2)
+        he = t.he.copy()
+        he[:, g.HE_SRC] = perm[t.he[:, g.HE_SRC]]
+        he[:, g.HE_TGT] = perm[t.he[:, g.HE_TGT]]
+        X = np.empty_like(t.X)
+        X[perm] = t.X
+        T = vtx.Tissue(he, nv, t.Lx, t.Ly)
+        ts = T.tile_stats()
+        print(part, ts)
+        assert ts["global_tiles"] > 0
+        assert part == "all" or ts["global_tiles"] < ts["tiles"]
+        Xd = _dev(X, dt)
+        P = vtx.Params.from_numpy(p, dtype=dt)
+        E, F, mf = T.energy_forces(Xd, P, mode=mode, want_maxf=True)
+        cf = T.cell_coeffs(Xd, P, mode=mode)
+        F2, _ = T.vertex_forces(Xd, P, cf, mode=mode, want_maxf=True)
+        assert torch.equal(F, F2)
+        assert mf.item() == F.abs().max().item()
+        m = oracle.Mesh(he, nv, t.Lx, t.Ly)
+        Eo, Fo = oracle.energy_forces(m, Xd.double().cpu().numpy(), p)
+        rel = abs(E.item() - Eo) / abs(Eo)
+        ferr = _force_err(F.double().cpu().numpy(), Fo)
+        errlog(f"fused evaluation {mode}, global-path tiles ({part} shuffled): energy "
+               "against the oracle (relative)", rel)
+        errlog(f"fused evaluation {mode}, global-path tiles ({part} shuffled): forces "
+               "(max |dF| / max |F|)", ferr)
+        assert rel < {"f32": 1e-5, "mixed": 1e-6, "f64": 1e-12}[mode]
+        assert ferr < {"f32": 1e-5, "mixed": 1e-5, "f64": 1e-10}[mode]
+
+
 def test_batch_schedules_agree(vtx):
     """The persistent schedule (256 and 1024 threads per tissue), the grid
     schedule and the autotuned choice give the same relaxations."""
