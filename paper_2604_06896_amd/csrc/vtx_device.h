@@ -133,8 +133,9 @@ __device__ __forceinline__ void star_gather(const PosT *__restrict__ X, const De
     }
 }
 
-// NOIMG: the three neighbours are known to carry the zero image.
-template <typename PosT, typename M, bool NOIMG = false>
+// NOIMG: the three neighbours are known to carry the zero image.  HVP: the
+// inverse lengths of the Hessian-vector product (len_inv_hvp).
+template <typename PosT, typename M, bool NOIMG = false, bool HVP = false>
 __device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<PosT, M> &L,
                                           Star<PosT, M> &s, PosT &xi, PosT &yi) {
     const PosT Lx = (PosT)t.Lx, Ly = (PosT)t.Ly;
@@ -150,7 +151,8 @@ __device__ __forceinline__ void star_math(const DevTissue &t, const StarLoad<Pos
         s.lam[k] = (M)L.lam[k];
         // a zero-length edge contributes its minimum-norm subgradient, 0
         M l, inv;
-        len_inv(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k], l, inv);
+        if (HVP) len_inv_hvp(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k], l, inv);
+        else len_inv(s.dx[k] * s.dx[k] + s.dy[k] * s.dy[k], l, inv);
         s.l[k] = l;
         s.inv[k] = inv;
         s.ux[k] = s.dx[k] * inv;
@@ -745,7 +747,7 @@ __device__ __forceinline__ void hvp_cell_row(const DevTissue &t, const PosT *__r
         dA += gx * vcx + gy * vcy;
         const C dx = rnx - rcx, dy = rny - rcy;
         const C l2 = dx * dx + dy * dy;
-        if (l2 > (C)0) dP += over_len(dx * (vnx - vcx) + dy * (vny - vcy), l2);
+        if (l2 > (C)0) dP += over_len_hvp(dx * (vnx - vcx) + dy * (vny - vcy), l2);
         rpx = rcx;
         rpy = rcy;
         rcx = rnx;
@@ -780,7 +782,7 @@ __device__ __forceinline__ double hvp_vertex_star(const DevTissue &t,
                                                   double &hx_out, double &hy_out) {
     Star<PosT, M> s;
     PosT xi, yi;
-    star_math<PosT, M>(t, L, s, xi, yi);
+    star_math<PosT, M, false, true>(t, L, s, xi, yi);
     const auto vi = ld2(v, i);
     M G[3], B[3], vx[3], vy[3];
 #pragma unroll
