@@ -221,7 +221,11 @@ def test_batched_lds_paths_with_many_sided_cells(vtx, small_equilibria):
     outs, infos = vtx.Batch(Ts).param_grad(Xs, Ps, dC_dX=[s[2] for s in singles],
                                            cg_tol=1e-10, block_threads=512)
     for (_, _, _, gref, iref), gb, inf in zip(singles, outs, infos):
-        assert (inf["status"], inf["cg_iters"]) == (iref["status"], iref["cg_iters"])
+        # the workgroup CG and the grid CG add their dot products in
+        # different orders, so the step at which the residual crosses 1e-10
+        # may differ by one
+        assert inf["status"] == iref["status"]
+        assert abs(inf["cg_iters"] - iref["cg_iters"]) <= 1, (inf, iref)
         assert np.abs(gb.cpu().numpy() - gref).max() < 1e-8 * np.abs(gref).max()
 
 
