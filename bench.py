@@ -44,6 +44,8 @@ METRIC = "vertex-force evals/s; param-gradients/s (batched adjoint vs plain) at 
 FLOOR_B_PER_VERTEX = 34   # positions in 8 + forces out 8 + 3-neighbour list 12 + lambda 6
 SLEEP_CYCLES = 240000     # device-side delay before the timed region (~1.5 ms on MI355X)
 COUNTERS = os.path.join(ROOT, "profiles", "eval_fused_1m_cells_counters.txt")
+SQ_COUNTERS = os.path.join(ROOT, "profiles", "eval_fused_1m_cells_sq_counters.txt")
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4   # 256 CUs x 4 SIMDs; a wave64 VALU op: 4 cycles
 
 
 def log(msg):
@@ -95,11 +97,9 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def read_traffic(path, sha):
-    """HBM bytes per fused-evaluation launch from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel
-    calibration), or None if the summary is missing or was taken on other
-    kernel sources."""
+def read_summary(path, sha, key):
+    """A figure `key: value` from a committed counter summary, or None if the
+    summary is missing or was taken on other kernel sources."""
     vals = {}
     try:
         with open(path) as f:
@@ -108,13 +108,26 @@ def read_traffic(path, sha):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
     except OSError:
-        return None, "no counter summary"
+        return None
     if vals.get("kernel_source_sha") != sha:
-        return None, "counters taken on other kernel sources"
+        return None
     try:
-        return float(vals["fused_eval_bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE"
+        return float(vals[key])
     except (KeyError, ValueError):
-        return None, "no fused-evaluation figure in the counter summary"
+        return None
+
+
+def read_traffic(path, sha):
+    """HBM bytes per fused-evaluation launch from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel
+    calibration), or None if the summary is missing or was taken on other
+    kernel sources."""
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    v = read_summary(path, sha, "fused_eval_bytes_per_launch")
+    if v is None:
+        return None, "counters taken on other kernel sources, or no fused-evaluation figure"
+    return v, "rocprofv3 FETCH_SIZE + WRITE_SIZE"
 
 
 # --------------------------------------------------------------- CPU baseline
@@ -504,6 +517,14 @@ def main():
             "vertex_pass_floor_frac": floor / v_ms / 1e6 / HBM_PEAK_GBS},
         "kernel_source_sha": sha,
     }
+    valu = read_summary(SQ_COUNTERS, sha, "valu_wave_instructions_per_launch")
+    roofline["alu"] = None if valu is None else {
+        "valu_wave_instructions": valu,
+        "issue_frac": valu * VALU_CYCLES / (SIMDS * CLOCK_HZ * f_ms / 1e3),
+        "basis": "SQ_INSTS_VALU of the committed counter summary (median over the kernel's "
+                 "dispatches with and without the energy sums) x 4 cycles per wave64 VALU "
+                 "instruction, over the 1024 SIMDs at 2.4 GHz for the fused kernel's "
+                 "measured time"}
     del F2, coeffs
     torch.cuda.empty_cache()
 
