@@ -76,10 +76,52 @@ __host__ __device__ inline bool cg_fast_fits(int64_t n_vert, int64_t n_cell, int
            cg_fast_lds_bytes<PosT, M>(n_vert, n_cell, n_he) <= lds_bytes;
 }
 
-// Conjugate gradients of one tissue in which thread i owns cells i + k B
-// (k < K) and vertices i + j B (j < 2K), B = blockDim.x.  What a step reads of
-// the topology (the cells' corner rows, the vertices' star entries and
-// tensions) is loaded once: the rows into LDS behind the arrays of
+// Cells of a tissue handed to the threads of the register-resident CG by
+// side count.  The cells, stably sorted by min(sides, 15), are cut into K
+// runs of ceil(n_cell / K); slot k of thread i takes entry i of run k,
+// counted from the front in even runs and from the back in odd ones.  The
+// cells of one slot across a wave then have about the same number of
+// corners (the wave walks them in step), and each thread's K cells about K
+// times the mean, so the waves finish the cell phase together.  `tmp`
+// holds n_cell ints.  cid[k] is the cell of the thread's slot k, -1 if the
+// run has no entry i.
+template <int K>
+__device__ __forceinline__ void cells_by_sides(const DevTissue &t, int *tmp, int *s_scan,
+                                               int (&cid)[K]) {
+    constexpr int kBuckets = 16;
+    const int tid = threadIdx.x, bd = blockDim.x, nc = t.n_cell;
+    int b[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int c = tid + i * bd;
+        b[i] = c < nc ? min(t.nsides[c], kBuckets - 1) : -1;
+    }
+    int base = 0;
+    for (int bucket = 0; bucket < kBuckets; ++bucket) {
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) cnt += b[i] == bucket ? 1 : 0;
+        int tot;
+        int at = base + block_exclusive_scan(cnt, s_scan, tot);
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (b[i] == bucket) tmp[at++] = tid + i * bd;
+        base += tot;
+    }
+    __syncthreads();
+    const int run = (nc + K - 1) / K;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int lo = i * run, len = min(run, nc - lo);
+        cid[i] = tid < len ? tmp[lo + ((i & 1) ? len - 1 - tid : tid)] : -1;
+    }
+    __syncthreads();  // `tmp` is free again
+}
+
+// Conjugate gradients of one tissue in which thread i owns K cells (given
+// by cells_by_sides) and vertices i + j B (j < 2K), B = blockDim.x.  What a
+// step reads of the topology (the cells' corner rows, the vertices' star
+// entries and tensions) is loaded once: the rows into LDS behind the arrays of
 // cg_lds_bytes (already resident), the stars into registers; the solution
 // and residual of the thread's own vertices stay in registers.  A step then
 // waits only on LDS and the workgroup's reductions.  The arithmetic and the
@@ -99,16 +141,18 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
     const M *capl = (const M *)(lds + o_c);
     M *auxl = (M *)(lds + o_a);
     int32_t *rowl = (int32_t *)(lds + o_r);
+    int cid[K];
+    cells_by_sides<K>(t, reinterpret_cast<int *>(ql), s_scan, cid);
     int n[K], lrb[K];
     PosT ka[K], kp[K];
     int rows_base = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const int c = tid + i * bd;
+        const int c = cid[i];
         int rb = 0;
         n[i] = 0;
         ka[i] = kp[i] = 0;
-        if (c < t.n_cell) {
+        if (c >= 0) {
             rb = t.row_ptr[c];
             n[i] = t.nsides[c];
             ka[i] = p.ka(c);
@@ -161,12 +205,11 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const int c = tid + i * bd;
             const int base = lrb[i];
-            if (c < t.n_cell)
+            if (n[i] > 0)
                 hvp_cell_row<PosT, M>(
                     t, Xl, ql, n[i], [&](int k) { return rowl[base + k]; }, ka[i], kp[i],
-                    auxl, c);
+                    auxl, cid[i]);
         }
         __syncthreads();
         double d = 0.0, aq[KV][2];
@@ -668,6 +711,10 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
         M *capl = (M *)(lds_dyn + 2 * xb);
         int32_t *rowl = (int32_t *)(lds_dyn + 2 * xb + a16(2 * (int64_t)nc * (int64_t)sizeof(M)));
         for (int k = tid; k < 2 * nv; k += bd) X0[k] = ((const PosT *)B.X)[k];
+        // the thread's cells, by side count (kept across T1 passes, which
+        // change a few cells' counts by one); X1 is free until the first step
+        int cid[K];
+        cells_by_sides<K>(t, reinterpret_cast<int *>(X1), s_scan, cid);
         int cn[K], lrb[K], grb[K];
         PosT ka[K], a0[K], kp[K], p0[K];
         int32_t sw[KV][3], sc[KV][3];
@@ -678,10 +725,10 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
             int rows_base = 0;
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                const int c = tid + i * bd;
+                const int c = cid[i];
                 grb[i] = 0;
                 cn[i] = 0;
-                if (c < nc) {
+                if (c >= 0) {
                     grb[i] = t.row_ptr[c];
                     cn[i] = t.nsides[c];
                 }
@@ -712,9 +759,9 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
         load_topology();
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const int c = tid + i * bd;
+            const int c = cid[i];
             ka[i] = a0[i] = kp[i] = p0[i] = 0;
-            if (c < nc) {
+            if (c >= 0) {
                 ka[i] = p.ka(c);
                 a0[i] = p.a0(c);
                 kp[i] = p.kp(c);
@@ -762,9 +809,9 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
             // cell pass
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                const int c = tid + i * bd;
+                const int c = cid[i];
                 const int base = lrb[i];
-                if (c < nc) {
+                if (c >= 0) {
                     PosT A, P;
                     cell_geom<PosT, PosT>(
                         t, Xc, cn[i], [&](int k) { return rowl[base + k]; }, grb[i], A, P,
