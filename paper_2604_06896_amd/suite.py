@@ -52,6 +52,23 @@ def single_100(log=print):
         out[name] = dict(r, s=dt, steps_per_s=r["iters"] / dt, max_iter=cap)
         log(f"100 cells {name}: status {r['status']}, {r['iters']} steps, T1 {r['n_t1']}, "
             f"max|F| {r['max_f']:.2e}, {dt:.2f}s")
+        if t1:
+            # the same relaxation as a batch of one: the whole loop in one
+            # workgroup (LDS-resident kernel) instead of two grid launches a step
+            T2 = V.Tissue.from_tissue(t)
+            X2 = torch.as_tensor(t.X, dtype=torch.float64, device="cuda")
+            B = V.Batch([T2])
+            _sync()
+            t0 = time.perf_counter()
+            rb = B.relax([X2], [P], mode="f64", eta=1e-2, tol=1e-6, max_iter=cap,
+                         t1_enable=True, l_min=0.01)[0]
+            _sync()
+            db = time.perf_counter() - t0
+            same = bool(torch.equal(X, X2)) and np.array_equal(T.topology(), T2.topology())
+            out["with_t1_batch_of_one"] = dict(rb, s=db, steps_per_s=rb["iters"] / db,
+                                               same_iterates_as_single=same)
+            log(f"100 cells with_t1 as a batch of one: status {rb['status']}, {rb['iters']} "
+                f"steps, T1 {rb['n_t1']}, {db:.2f}s, same positions and topology: {same}")
     return out
 
 
