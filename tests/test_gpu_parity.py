@@ -1061,6 +1061,61 @@ def test_batch_adjoint_lds_and_global_paths(vtx, block_threads):
         assert err.value.code == -1
 
 
+def test_side_count_cell_order_on_ragged_tissues(vtx, oracle, errlog):
+    """The LDS-resident relaxation and the register-resident CG give each
+    thread one cell from each end of the cells sorted by side count.  On
+    random tissues of odd cell counts (runs of unequal length; 3- to
+    11-sided cells): the batched relaxation with T1 equals the
+    single-tissue loop bit for bit (positions, topology, step and T1
+    counts), and the batched adjoint at its end points equals the
+    single-tissue (grid kernel) solve and, on the two smallest, the
+    oracle."""
+    rng = np.random.default_rng(71)
+    cases = []
+    for n in (9, 21, 333):
+        t = g.random_tissue(n, np.sqrt(n), rng=rng)
+        p = g.uniform_params(t, P0=3.7)
+        p.lam = rng.uniform(0.05, 0.15, t.n_edge)
+        cases.append((t, p))
+    opts = dict(eta=3e-3, tol=1e-9, max_iter=400000, t1_enable=True, l_min=0.01)
+    Ps = [vtx.Params.from_numpy(p) for _, p in cases]
+    Ts, Xs, rs = [], [], []
+    for (t, _), P in zip(cases, Ps):
+        T = vtx.Tissue.from_tissue(t)
+        X = _dev(t.X)
+        rs.append(T.relax(X, P, mode="f64", **opts))
+        Ts.append(T); Xs.append(X)
+    Tb = [vtx.Tissue.from_tissue(t) for t, _ in cases]
+    Xb = [_dev(t.X) for t, _ in cases]
+    res = vtx.Batch(Tb).relax(Xb, Ps, mode="f64", block_threads=512, **opts)
+    for T, X, r, Tq, Xq, rb in zip(Ts, Xs, rs, Tb, Xb, res):
+        assert r["status"] == 0, r
+        assert (rb["status"], rb["iters"], rb["n_t1"]) == (r["status"], r["iters"], r["n_t1"])
+        assert torch.equal(X, Xq)
+        assert np.array_equal(T.topology(), Tq.topology())
+    bs = [_dev(rng.normal(0, 1e-3, tuple(X.shape))) for X in Xs]
+    singles = []
+    for T, X, P, b in zip(Ts, Xs, Ps, bs):
+        gs, info = T.param_grad(X, P, dC_dX=b, cg_tol=1e-10)
+        assert info["status"] == 0, info
+        singles.append(gs.cpu().numpy())
+    outs, infos = vtx.Batch(Tb).param_grad(Xb, Ps, dC_dX=bs, cg_tol=1e-10, block_threads=512)
+    worst = 0.0
+    for k, (gs, gb, inf) in enumerate(zip(singles, outs, infos)):
+        assert inf["status"] == 0, inf
+        gb = gb.cpu().numpy()
+        worst = max(worst, np.abs(gb - gs).max() / np.abs(gs).max())
+        if k < 2:
+            t, p = cases[k]
+            m = oracle.Mesh(Tb[k].topology(), t.n_vert, t.Lx, t.Ly)
+            go, _ = oracle.adjoint_grad(m, Xb[k].cpu().numpy(), p, bs[k].cpu().numpy(),
+                                        tol=1e-10)
+            assert np.abs(gb - go).max() < 1e-7 * np.abs(go).max()
+    errlog("batched register-resident CG vs single (grid) solve, odd cell counts "
+           "(max |dg| / max |g|, worst tissue)", worst)
+    assert worst < 1e-9
+
+
 @pytest.mark.parametrize("parts", [-1, -2, -4, -8])
 @pytest.mark.parametrize("theta", ["lambda", "P0"])
 def test_batch_adjoint_multiblock(vtx, oracle, errlog, small_equilibria, theta, parts):
