@@ -142,6 +142,8 @@ __device__ __forceinline__ int batch_cg_fast(const DevTissue &t, const DevParams
     M *auxl = (M *)(lds + o_a);
     int32_t *rowl = (int32_t *)(lds + o_r);
     int cid[K];
+    // q is not set yet; its 2 n_vert doubles hold the n_cell <= n_vert ints
+    // (three corners per vertex, at least three per cell)
     cells_by_sides<K>(t, reinterpret_cast<int *>(ql), s_scan, cid);
     int n[K], lrb[K];
     PosT ka[K], kp[K];
@@ -713,6 +715,7 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
         for (int k = tid; k < 2 * nv; k += bd) X0[k] = ((const PosT *)B.X)[k];
         // the thread's cells, by side count (kept across T1 passes, which
         // change a few cells' counts by one); X1 is free until the first step
+        // and its 2 n_vert positions hold the n_cell <= n_vert ints
         int cid[K];
         cells_by_sides<K>(t, reinterpret_cast<int *>(X1), s_scan, cid);
         int cn[K], lrb[K], grb[K];
