@@ -93,6 +93,28 @@ __device__ __forceinline__ double block_allsum(double v, double *sh) {
     return r;
 }
 
+// Two block_allsum sums with one pair of barriers (each component added in
+// the same order as block_allsum's); workgroups of up to 512 threads, `sh`
+// holds 16 doubles.
+__device__ __forceinline__ double2 block_allsum2(double a, double b, double *sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();  // `sh` may still be read by the previous reduction
+    if (lane == 0) {
+        sh[wid] = a;
+        sh[8 + wid] = b;
+    }
+    __syncthreads();
+    double ra = 0.0, rb = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) {
+        ra += sh[w];
+        rb += sh[8 + w];
+    }
+    return double2{ra, rb};
+}
+
 // Exclusive prefix sum of one int per thread over the workgroup (up to 16
 // waves); `sh` holds 16 ints.  Also returns the total.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total) {

@@ -667,6 +667,7 @@ __host__ __device__ inline int64_t relax_lds_bytes(int64_t n_vert, int64_t n_cel
 // Cells (and twice as many vertices) per thread of k_batch_relax_lds.
 constexpr int kRelaxLdsK = 2;
 constexpr int kRelaxLdsThreads = 512;
+static_assert(kRelaxLdsThreads <= 512, "block_allsum2 holds the sums of eight waves");
 
 // Batched relaxation of tissues of at most two cells and four vertices per
 // thread of a 512-thread workgroup whose two position buffers, cell
@@ -771,12 +772,14 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                 p0[i] = p.p0(c);
             }
         }
+        // a nudge (EP) never comes with T1: the T1 forms compile it out
+        const bool nudged = !T1 && B.beta != 0.0;
         double nt[KV][2];  // nudge target (v2v) or linear cost gradient
 #pragma unroll
         for (int j = 0; j < KV; ++j) {
             const int v = tid + j * bd;
             nt[j][0] = nt[j][1] = 0.0;
-            if (v < nv && B.beta != 0.0) {
+            if (v < nv && nudged) {
                 if (B.Xt) {
                     const PosT *Xt = (const PosT *)B.Xt;
                     nt[j][0] = (double)Xt[2 * (int64_t)v];
@@ -833,22 +836,25 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                     __syncthreads();
                 }
             }
-            // mean of the nudge gradient over the vertices
-            double mx = 0.0, my = 0.0;
-            if (B.beta != 0.0) {
+            // nudge gradient at the own vertices (kept for the vertex pass)
+            // and its mean over the vertices
+            double mx = 0.0, my = 0.0, ncx[KV], ncy[KV];
+#pragma unroll
+            for (int j = 0; j < KV; ++j) ncx[j] = ncy[j] = 0.0;
+            if (nudged) {
                 double sx = 0.0, sy = 0.0;
 #pragma unroll
                 for (int j = 0; j < KV; ++j) {
                     const int v = tid + j * bd;
                     if (v < nv) {
-                        double cx, cy;
-                        nudge(j, Xc, v, cx, cy);
-                        sx += cx;
-                        sy += cy;
+                        nudge(j, Xc, v, ncx[j], ncy[j]);
+                        sx += ncx[j];
+                        sy += ncy[j];
                     }
                 }
-                mx = block_allsum(sx, sh) * inv_n;
-                my = block_allsum(sy, sh) * inv_n;
+                const double2 s2 = block_allsum2(sx, sy, sh);
+                mx = s2.x * inv_n;
+                my = s2.y * inv_n;
             }
             // vertex pass with the step
             double mf = 0.0;
@@ -872,11 +878,9 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
                     M fx, fy;
                     star_force<PosT, M>(s, fx, fy);
                     double gx = fx, gy = fy;
-                    if (B.beta != 0.0) {
-                        double cx, cy;
-                        nudge(j, Xc, v, cx, cy);
-                        gx -= B.beta * (cx - mx);
-                        gy -= B.beta * (cy - my);
+                    if (nudged) {
+                        gx -= B.beta * (ncx[j] - mx);
+                        gy -= B.beta * (ncy[j] - my);
                     }
                     mf = fmax(mf, fmax(fabs(gx), fabs(gy)));
                     if (!(gx == gx) || !(gy == gy)) mf = INFINITY;
