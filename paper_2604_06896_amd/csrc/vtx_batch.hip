@@ -794,10 +794,15 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
         __syncthreads();
         const double inv_n = 1.0 / (double)nv;
         // gradient of the nudge cost at own vertex j (as nudge_grad)
+        // (min_image returns d itself for |d| <= L/4: d/L rounds into
+        // [-1/4, 1/4], so the floor is +0; such d skip its division)
+        auto near_image = [](double d, double L) {
+            return fabs(d) <= 0.25 * L ? d : min_image(d, L);
+        };
         auto nudge = [&](int j, const PosT *Xc, int v, double &cx, double &cy) {
             if (B.Xt) {
-                cx = min_image((double)Xc[2 * v] - nt[j][0], t.Lx) * inv_n;
-                cy = min_image((double)Xc[2 * v + 1] - nt[j][1], t.Ly) * inv_n;
+                cx = near_image((double)Xc[2 * v] - nt[j][0], t.Lx) * inv_n;
+                cy = near_image((double)Xc[2 * v + 1] - nt[j][1], t.Ly) * inv_n;
             } else {
                 cx = nt[j][0];
                 cy = nt[j][1];
