@@ -835,9 +835,13 @@ __global__ __launch_bounds__(kRelaxLdsThreads) void k_batch_relax_lds(
             if (T1) {
                 const int ncand = (int)s_cnt;
                 if (ncand > 0) {
+                    const int64_t swaps0 = st.n_t1;
                     batch_t1_pass_lds<PosT, M>(&B, Xc, capl, ncand, o.l_min, o.l_new, sort_buf,
                                                extra, scan, &st);
-                    load_topology();
+                    // rows and stars change only with an exchange; a pass of
+                    // stretches alone moves positions and rewrites cell
+                    // coefficients, both in LDS already
+                    if (st.n_t1 != swaps0) load_topology();
                     __syncthreads();
                 }
             }
