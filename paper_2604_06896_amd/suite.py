@@ -420,11 +420,9 @@ def finite_differences(Ts, ts, Xs, Ps, Xts, n_dir=8, h=1e-3, beta=1e-3, tol=1e-1
     return res
 
 
-def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000,
-                         log=print):
-    """The inverse workload's batched adjoint on its own: targets and
-    predictions relaxed (batched, FP64, T1), then one batched adjoint
-    launch (CG to 1e-8).  A short program for kernel counters."""
+def _inverse_equilibria(n_tissue, n_cell, seed, relax_max_iter):
+    """The inverse workload's targets and predictions relaxed (batched,
+    FP64, T1, to 1e-6): tissues, predicted equilibria, targets, parameters."""
     work = g.workload_inverse(seed=seed, n_tissue=n_tissue, n_cell=n_cell)
     Ts_t = [V.Tissue.from_tissue(t) for t, _, _ in work]
     Ts = [V.Tissue.from_tissue(t) for t, _, _ in work]
@@ -438,6 +436,15 @@ def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000
     V.Batch(Ts_t).relax(Xt, [prm(ps) for _, ps, _ in work], mode="f64", **ropts)
     Pi = [prm(pi) for _, _, pi in work]
     V.Batch(Ts).relax(Xs, Pi, mode="f64", **ropts)
+    return Ts, Xs, Xt, Pi
+
+
+def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000,
+                         log=print):
+    """The inverse workload's batched adjoint on its own: targets and
+    predictions relaxed (batched, FP64, T1), then one batched adjoint
+    launch (CG to 1e-8).  A short program for kernel counters."""
+    Ts, Xs, Xt, Pi = _inverse_equilibria(n_tissue, n_cell, seed, relax_max_iter)
     b = [T.v2v(X, Y)[1] for T, X, Y in zip(Ts, Xs, Xt)]
     _sync()
     t0 = time.perf_counter()
@@ -450,13 +457,33 @@ def batched_adjoint_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000
     return dt
 
 
+def batched_ep_once(n_tissue=64, n_cell=1000, seed=501, relax_max_iter=2000000,
+                    ep_steps=20000, log=print):
+    """The inverse workload's set-up relaxations, then one batched centred EP
+    (beta = 1e-3, v2v nudge to the targets) whose nudged relaxations run a
+    fixed number of steps.  A short program for kernel counters."""
+    Ts, Xs, Xt, Pi = _inverse_equilibria(n_tissue, n_cell, seed, relax_max_iter)
+    _sync()
+    t0 = time.perf_counter()
+    V.Batch(Ts).param_grad(Xs, Pi, X_target=Xt, method="ep", beta=1e-3,
+                           ep_relax=dict(eta=3e-3, tol=0.0, max_iter=ep_steps))
+    _sync()
+    dt = time.perf_counter() - t0
+    log(f"batched centred EP: {n_tissue} tissues, {ep_steps} nudged steps each sign, "
+        f"{dt:.2f} s")
+    return dt
+
+
 if __name__ == "__main__":
-    # short programs for kernel counters: the batched adjoint of the inverse
-    # workload, or the 512-tissue batched relaxation capped at 2e4 iterations
+    # short programs for kernel counters: the batched adjoint or a
+    # fixed-length batched centred EP of the inverse workload, or the
+    # 512-tissue batched relaxation capped at 2e4 iterations
     import sys
     if sys.argv[1:] == ["adjoint"]:
         batched_adjoint_once()
+    elif sys.argv[1:] == ["ep"]:
+        batched_ep_once()
     elif sys.argv[1:] == ["relax"]:
         batched_relax(max_iter=20000, plain_sample=0, block_threads=1024)
     else:
-        raise SystemExit("usage: python -m paper_2604_06896_amd.suite adjoint|relax")
+        raise SystemExit("usage: python -m paper_2604_06896_amd.suite adjoint|ep|relax")
