@@ -18,12 +18,12 @@ using namespace vtx;
 struct vtx_batch_s {
     std::vector<vtx_tissue> ts;
     std::vector<int32_t> order;  // tissue indices by descending size
-    void *items;                 // device BatchItem[n]
+    void *items;                 // device BatchItem[2n] (centred EP: both nudges)
     void *gitems;                // device GradItem[n]
     void **xm_list;              // device pointer list (EP minus states)
-    int32_t *order_d;
+    int32_t *order_d;            // device [2n]: order, then order + n
     unsigned int *queue;
-    vtx_relax_result *res_d;
+    vtx_relax_result *res_d;     // device [2n]
     vtx_grad_result *gres_d;
     void *mb_groups;             // device MbGroup[n] (multi-workgroup adjoint)
     int32_t *order2_d;           // device tissue list of a second launch
@@ -1284,12 +1284,11 @@ int relax_split(vtx_batch b, int mode, const BatchItem *it, const BatchOpts &bo,
     });
 }
 
-int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
-                    const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
-                    double beta, int block_threads, vtx_relax_result *res, hipStream_t s,
-                    int split_K = 0) {
+// The batch's items for positions X (nudge beta towards Xt, or along g_lin)
+// into items[0, n).
+int make_items(vtx_batch b, void *const *X, const vtx_params *p, const void *const *Xt,
+               const double *const *g_lin, double beta, BatchItem *items) {
     const int n = (int)b->ts.size();
-    std::vector<BatchItem> items(n);
     for (int i = 0; i < n; ++i) {
         if (!X[i]) return set_error(VTX_E_ARG, "null X in batch");
         const Workspace &w = tissue_ws(b->ts[i]);
@@ -1305,6 +1304,36 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
         it.beta = beta;
         if (beta != 0.0 && !it.Xt && !it.g_lin) return set_error(VTX_E_ARG, "nudge without a cost");
     }
+    return VTX_OK;
+}
+
+// As vtx_relax: a failed tissue reports NOT_CONVERGED and the call returns
+// the error of the first failed tissue, naming it.
+int relax_statuses(vtx_relax_result *res, int n) {
+    int err = VTX_OK, first = -1;
+    for (int i = 0; i < n; ++i) {
+        if (res[i].status == VTX_E_NONFINITE || res[i].status == VTX_E_CAPACITY) {
+            if (first < 0) {
+                first = i;
+                err = res[i].status;
+            }
+            res[i].status = VTX_NOT_CONVERGED;
+        }
+    }
+    if (first < 0) return VTX_OK;
+    const std::string what = err == VTX_E_NONFINITE ? "non-finite forces" : "T1 pass overflow";
+    const std::string msg = what + " in batched relaxation of tissue " + std::to_string(first);
+    return set_error(err, msg.c_str());
+}
+
+int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
+                    const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
+                    double beta, int block_threads, vtx_relax_result *res, hipStream_t s,
+                    int split_K = 0) {
+    const int n = (int)b->ts.size();
+    std::vector<BatchItem> items(n);
+    int rc0 = make_items(b, X, p, Xt, g_lin, beta, items.data());
+    if (rc0) return rc0;
     hipError_t e = hipMemcpyAsync(b->items, items.data(), sizeof(BatchItem) * n,
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e);
@@ -1367,22 +1396,57 @@ int batch_relax_run(vtx_batch b, int mode, void *const *X, const vtx_params *p,
     e = hipMemcpyAsync(res, b->res_d, sizeof(vtx_relax_result) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
-    // As vtx_relax: a failed tissue reports NOT_CONVERGED and the call
-    // returns the error of the first failed tissue, naming it.
-    int err = VTX_OK, first = -1;
-    for (int i = 0; i < n; ++i) {
-        if (res[i].status == VTX_E_NONFINITE || res[i].status == VTX_E_CAPACITY) {
-            if (first < 0) {
-                first = i;
-                err = res[i].status;
-            }
-            res[i].status = VTX_NOT_CONVERGED;
-        }
-    }
-    if (first < 0) return VTX_OK;
-    const std::string what = err == VTX_E_NONFINITE ? "non-finite forces" : "T1 pass overflow";
-    const std::string msg = what + " in batched relaxation of tissue " + std::to_string(first);
-    return set_error(err, msg.c_str());
+    return relax_statuses(res, n);
+}
+
+constexpr int kPlanDoesNotApply = 1;
+
+// Centred EP's two nudged relaxations (+beta and -beta about X*, from Xp
+// and Xm) as one launch of 2n items when every tissue takes the
+// LDS-resident kernel: there the two items of a tissue share no global
+// scratch (positions and coefficients live in LDS; no T1), so each runs
+// exactly as it would alone and the 2n run side by side.  Returns
+// kPlanDoesNotApply, having launched nothing, otherwise.
+int batch_relax_pm(vtx_batch b, int mode, void *const *Xp, void *const *Xm, const vtx_params *p,
+                   const vtx_relax_opts *o, const void *const *Xt, const double *const *g_lin,
+                   double beta, int block_threads, vtx_relax_result *rp, vtx_relax_result *rm,
+                   hipStream_t s) {
+    if (o->t1_enable || (block_threads != 0 && block_threads != kRelaxLdsThreads))
+        return kPlanDoesNotApply;
+    int lds = 0, rc;
+    if (mode == VTX_F32) rc = relax_lds_plan<float, float, false>(b, &lds);
+    else if (mode == VTX_F64) rc = relax_lds_plan<double, double, false>(b, &lds);
+    else rc = relax_lds_plan<double, float, false>(b, &lds);
+    if (rc) return rc;
+    if (lds == 0) return kPlanDoesNotApply;
+    const int n = (int)b->ts.size();
+    std::vector<BatchItem> items(2 * (size_t)n);
+    if ((rc = make_items(b, Xp, p, Xt, g_lin, beta, items.data()))) return rc;
+    if ((rc = make_items(b, Xm, p, Xt, g_lin, -beta, items.data() + n))) return rc;
+    hipError_t e = hipMemcpyAsync(b->items, items.data(), sizeof(BatchItem) * 2 * n,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    const BatchOpts bo{o->eta, o->tol, o->l_min, o->l_new, o->patience, o->max_iter, 0};
+    const BatchItem *it = (const BatchItem *)b->items;
+    auto launch = [&](auto kern, hipStream_t cs) {
+        hipLaunchKernelGGL(kern, dim3(2 * n), dim3(kRelaxLdsThreads), (size_t)lds, cs, it,
+                           b->order_d, 2 * n, b->queue, bo, b->res_d);
+    };
+    rc = run_graph(b, s, [&](hipStream_t cs) {
+        if (mode == VTX_F32) launch(k_batch_relax_lds<float, float, false>, cs);
+        else if (mode == VTX_F64) launch(k_batch_relax_lds<double, double, false>, cs);
+        else launch(k_batch_relax_lds<double, float, false>, cs);
+    });
+    if (rc) return rc;
+    std::vector<vtx_relax_result> r(2 * (size_t)n);
+    e = hipMemcpyAsync(r.data(), b->res_d, sizeof(vtx_relax_result) * 2 * n,
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    std::copy(r.begin(), r.begin() + n, rp);
+    std::copy(r.begin() + n, r.end(), rm);
+    if ((rc = relax_statuses(rp, n))) return rc;
+    return relax_statuses(rm, n);
 }
 
 // Parts per tissue of the split schedule when the caller leaves it open:
@@ -1422,17 +1486,22 @@ int vtx_batch_create(const vtx_tissue *ts, int32_t n, vtx_batch *out) {
     std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
         return tissue_size(b->ts[a]) > tissue_size(b->ts[c]);
     });
-    hipError_t e = hipMalloc(&b->items, sizeof(BatchItem) * n);
+    std::vector<int32_t> order2(2 * (size_t)n);  // order, then the same + n
+    for (int i = 0; i < n; ++i) {
+        order2[i] = b->order[i];
+        order2[n + i] = b->order[i] + n;
+    }
+    hipError_t e = hipMalloc(&b->items, sizeof(BatchItem) * 2 * n);
     if (e == hipSuccess) e = hipMalloc(&b->gitems, sizeof(GradItem) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->xm_list, sizeof(void *) * n);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->order_d, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->order_d, sizeof(int32_t) * 2 * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->queue, sizeof(unsigned int));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->res_d, sizeof(vtx_relax_result) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->res_d, sizeof(vtx_relax_result) * 2 * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->gres_d, sizeof(vtx_grad_result) * n);
     if (e == hipSuccess) e = hipMalloc(&b->mb_groups, mb_group_bytes() * n);
     if (e == hipSuccess) e = hipMalloc((void **)&b->order2_d, sizeof(int32_t) * n);
     if (e == hipSuccess)
-        e = hipMemcpy(b->order_d, b->order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+        e = hipMemcpy(b->order_d, order2.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         vtx_batch_destroy(b);
@@ -1703,14 +1772,23 @@ int vtx_batch_param_grad(vtx_batch b, int32_t mode, void *const *X_star, const v
     // -block_threads workgroups
     const int split = block_threads < 0 ? -block_threads : 0;
     const int bt = block_threads < 0 ? 0 : block_threads;
-    // first-order EP: one relaxation nudged by beta; the other state stays X*
-    rc = batch_relax_run(b, mode, Xp.data(), p, &o->ep_relax, X_target, X_target ? nullptr : dC_dX,
-                         centred ? 0.5 * o->beta : o->beta, bt, rp.data(), s, split);
-    if (rc) return rc;
-    if (centred) {
-        rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target,
-                             X_target ? nullptr : dC_dX, -0.5 * o->beta, bt, rm.data(), s, split);
+    rc = kPlanDoesNotApply;
+    if (centred && split == 0)  // both nudges in one launch where it applies
+        rc = batch_relax_pm(b, mode, Xp.data(), Xm.data(), p, &o->ep_relax, X_target,
+                            X_target ? nullptr : dC_dX, 0.5 * o->beta, bt, rp.data(), rm.data(), s);
+    if (rc != kPlanDoesNotApply && rc != VTX_OK) return rc;
+    if (rc == kPlanDoesNotApply) {
+        // first-order EP: one relaxation nudged by beta; the other state stays X*
+        rc = batch_relax_run(b, mode, Xp.data(), p, &o->ep_relax, X_target,
+                             X_target ? nullptr : dC_dX, centred ? 0.5 * o->beta : o->beta, bt,
+                             rp.data(), s, split);
         if (rc) return rc;
+        if (centred) {
+            rc = batch_relax_run(b, mode, Xm.data(), p, &o->ep_relax, X_target,
+                                 X_target ? nullptr : dC_dX, -0.5 * o->beta, bt, rm.data(), s,
+                                 split);
+            if (rc) return rc;
+        }
     }
     for (int i = 0; i < n; ++i) items[i].X = Xp[i];
     e = hipMemcpyAsync(b->gitems, items.data(), sizeof(GradItem) * n, hipMemcpyHostToDevice, s);
