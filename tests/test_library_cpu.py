@@ -142,3 +142,24 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_minimum_image_is_identity_within_a_quarter_box():
+    """The LDS-resident relaxation skips the minimum-image division for
+    |d| <= L/4: there d/L rounds into [-1/4, 1/4], floor(d/L + 1/2) is +0
+    and d - L * floor(d/L + 1/2) returns d bit for bit (signed zero and
+    subnormals included).  IEEE division and floor behave the same on the
+    host, so the identity is checked here on random and boundary values."""
+    rng = np.random.default_rng(5)
+    for L in (31.6227766016838, 1.0, 3.0, 1000.0, np.sqrt(20.0), 7.0 / 3.0):
+        q = 0.25 * L
+        edge = np.array([q, -q, np.nextafter(q, 0.0), -np.nextafter(q, 0.0), 0.0, -0.0,
+                         5e-324, -5e-324, 1e-300, -1e-300])
+        d = np.concatenate([rng.uniform(-q, q, 200_000), edge])
+        assert np.all(np.abs(d) <= q)
+        r = d - L * np.floor(d / L + 0.5)
+        assert np.array_equal(r.view(np.int64), d.view(np.int64))
+        # beyond half a box the formula wraps (the shortcut's L/4 bound is a
+        # conservative one): at three quarters of a box it returns d -/+ L
+        far = np.array([0.75 * L, -0.75 * L])
+        assert not np.array_equal(far - L * np.floor(far / L + 0.5), far)
