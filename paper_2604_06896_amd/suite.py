@@ -54,7 +54,7 @@ def single_100(log=print):
             f"max|F| {r['max_f']:.2e}, {dt:.2f}s")
         if t1:
             # the same relaxation as a batch of one: the whole loop in one
-            # workgroup (LDS-resident kernel) instead of two grid launches a step
+            # workgroup (LDS-resident kernel) instead of three launches a step
             T2 = V.Tissue.from_tissue(t)
             X2 = torch.as_tensor(t.X, dtype=torch.float64, device="cuda")
             B = V.Batch([T2])
